@@ -345,7 +345,9 @@ def radial_solve_modes(p, m, kk, Xn, Nn, Nq, dt, c=0.5, walls=True,
       6. influence matrix: lambda = -A^-1 beta(X0), A = [beta(X1) beta(X2)],
          beta = wall values of div X; X = X0 + sum lambda_j X_j, p likewise;
       7. mode (0,0): u_r = 0, u_theta with L_1 and u_z with L_0 under the wall
-         speeds; p^00 from D1 p = c N^q_r + (1-c) N^n_r with p(r_i) = 0;
+         speeds; p^00 from dp/dr = F_r = c N^q_r + (1-c) N^n_r in divergence
+         form, (D2 + D1/r) p = (D1 + 1/r) F_r inside, p(r_i) = 0, D1 p = F_r
+         at r_o;
       8. T: (I/dt - (c/Pr) L_m) T = f_T with T = +-1/2 at the walls in (0,0).
     Returns (X [F][N_r][B], p [N_r][B])."""
     if r is None:
@@ -470,13 +472,17 @@ def radial_solve_modes(p, m, kk, Xn, Nn, Nq, dt, c=0.5, walls=True,
         Xout[0][:, zi] = 0.0
         Xout[1][:, zi] = ut.transpose(0, 1)
         Xout[2][:, zi] = uz.transpose(0, 1)
-        # pressure head of the mean flow: D1 p = c N^q_r + (1-c) N^n_r, p(r_i) = 0
+        # pressure head of the mean flow, dp/dr = F_r = c N^q_r + (1-c) N^n_r,
+        # in divergence form: (D2 + D1/r) p = (D1 + 1/r) F_r inside,
+        # p(r_i) = 0, D1 p = F_r at r_o
         fr = (c * Nq[0][:, zi] + (1 - c) * Nn[0][:, zi]).transpose(0, 1)
-        Pm = D1.clone()
+        Pm = D2 + D1 / r[:, None]
         Pm[0, :] = 0.0
         Pm[0, 0] = 1.0
-        rhs = fr.clone()
+        Pm[-1, :] = D1[-1]
+        rhs = d1(fr) + inv_r * fr
         rhs[:, 0] = 0.0
+        rhs[:, -1] = fr[:, -1]
         Pz = _rsolve(Pm[None].expand(zi.numel(), n, n), rhs[:, :, None])[..., 0]
         Pout[:, zi] = Pz.transpose(0, 1)
     if p.heated:

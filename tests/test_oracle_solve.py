@@ -124,7 +124,9 @@ def test_influence_matrix_equals_monolithic_solve(heated):
 
 def test_mode00_reading():
     """(0,0): u_r = 0; u_theta solves the L_1 Helmholtz problem with the wall
-    speeds, u_z the L_0 problem with zero walls; p solves D1 p = f_r, p(r_i)=0."""
+    speeds, u_z the L_0 problem with zero walls; the mean pressure head solves
+    dp/dr = F_r in divergence form with p(r_i) = 0, so that for a smooth F_r
+    it converges to the integral of F_r."""
     p = O.Params(0.5, 50.0, -10.0, 0.0, 1.0, 16, 4, 7, 2 * math.pi)
     r = O.radial_grid(p)
     D1, D2 = O.fd_matrices(p, r)
@@ -140,10 +142,20 @@ def test_mode00_reading():
     res = ut / dt - c * L1 @ ut - f
     assert float(res[1:-1].abs().max()) < 1e-9 * float(f.abs().max())
     assert abs(complex(ut[0]) - 50.0) < 1e-13 and abs(complex(ut[-1]) + 10.0) < 1e-13
-    dp = D1.to(torch.complex128) @ P[:, 0]
-    fr = c * Nq[0, :, 0] + (1 - c) * Nn[0, :, 0]
-    assert float((dp - fr)[1:].abs().max()) < 1e-9 * float(fr.abs().max())
     assert abs(complex(P[0, 0])) < 1e-14
+    # smooth radial force: p converges to the integral of F_r from r_i
+    errs = []
+    for n in (16, 24, 32):
+        q = O.Params(0.5, 0.0, 0.0, 0.0, 1.0, n, 4, 7, 2 * math.pi)
+        rr = O.radial_grid(q)
+        Fr = torch.cos(3 * rr).to(torch.complex128)[:, None]
+        z = torch.zeros((3, n, 1), dtype=torch.complex128)
+        Nn2 = z.clone()
+        Nn2[0] = Fr
+        _, P2 = O.radial_solve_modes(q, torch.tensor([0]), torch.tensor([q.K]), z, Nn2, Nn2, dt, c)
+        exact = (torch.sin(3 * rr) - math.sin(3 * q.r_i)) / 3
+        errs.append(float((P2[:, 0].real - exact).abs().max()))
+    assert errs[2] < 1e-9 and errs[0] > errs[1] > errs[2]
 
 
 def _bessel_roots(ri, ro, count):
