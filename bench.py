@@ -1,0 +1,221 @@
+"""Benchmark of the Taylor--Couette time step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Workload (default tc-heated-n64): heated Taylor--Couette, eta = 0.71,
+Re_i = 100, Re_o = 0, Ra = 1e4, Pr = 0.7, N_r = 64, 64 x 127 Fourier modes
+(192 x 192 padded grid), seeded synthetic initial state, dynamic time step
+(CFL 0.5).  One step = nonlinear term + predictor solve + nonlinear term +
+corrector solve.  Prints one JSON line: mixed-precision steps/s (value), the
+FP64 steps/s on the same grid, the mixed-vs-FP64 error per field, the
+roofline figures of the dominant kernel (HIP events on the library stream)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("time steps/s per grid, mixed vs FP64 at stated error; "
+          "adjoint/forward cost ratio")
+HBM_PEAK_GBS = 8000.0
+
+
+def _field_bytes(w):
+    return w["N_r"] * w["M_theta"] * w["M_z"] * 16
+
+
+def kernel_bytes(name, w, prec):
+    """Algorithmic HBM bytes of one launch of each kernel (compulsory reads and
+    writes of its inputs and outputs, each array counted once)."""
+    F = 4 if w["Ra"] != 0 else 3
+    n_in = 9 if F == 4 else 6
+    S = _field_bytes(w)
+    esz = 8 if prec == "mixed" else 16
+    K = (w["M_z"] - 1) // 2
+    I = w["N_r"] * w["M_theta"] * 3 * (K + 1) * esz
+    kp1 = K + 1
+    fac_row = 9 * 8
+    nops_v = (w["M_theta"] + 1) * kp1
+    nops_m = w["M_theta"] * kp1
+    if name == "zinv":
+        return F * S + n_in * I
+    if name == "theta":
+        return (n_in + F) * I
+    if name == "zfwd":
+        return F * I + F * S + (S if F == 4 else 0)
+    if name == "rhs":
+        return 3 * F * S + F * S
+    if name == "div":
+        return 3 * S + S
+    if name == "solve_pt":
+        b = 2 * S + nops_m * w["N_r"] * fac_row
+        if F == 4:
+            b += 2 * S + nops_m * w["N_r"] * fac_row
+        return b
+    nmodes = w["M_theta"] * w["M_z"]
+    if name == "solve_vel":
+        return 3 * S + S + 3 * S + nops_v * w["N_r"] * fac_row
+    if name == "influence":
+        return 3 * 18 * nmodes * 16 + nops_m * 32 + nmodes * 32
+    if name == "finalize":
+        return (F + 1) * S + nmodes * 32 + nops_m * 8 * w["N_r"] * 8 + F * S
+    return 0
+
+
+def run_gpu(args, wname):
+    import torch
+
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+
+    w = WORKLOADS[wname]
+    torch.cuda.set_device(0)
+    ctx = nsc.Context(*params(wname))
+    amps = amplitudes(wname).cuda()
+    u0 = ctx.initial_state(amps)
+    dt_max = w["dt"]
+    if w["dynamic"]:
+        _, c = ctx.nonlinear(u0, cfl=True)
+        dt0 = min(dt_max, 0.5 * float(c.cpu()[0]))
+    else:
+        dt0 = w["dt"]
+
+    def run(prec, steps, warmup, profile=False):
+        ctx.set_precision(prec)
+        ctx.set_timestep(dt=dt0, dynamic=w["dynamic"], cfl=0.5, dt_max=dt_max)
+        u = u0.clone()
+        dt = dt0
+        for _ in range(warmup):
+            dt = ctx.step(u, dt)
+        torch.cuda.synchronize()
+        if profile:
+            ctx.timings()
+            ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dt = ctx.step(u, dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tim = None
+        if profile:
+            ctx.set_profiling(False)
+            tim = ctx.timings()
+        return el, u, dt, tim
+
+    K, W = args.steps, args.warmup
+    # untimed warm-up run of both precisions (first factorisation, code load)
+    run("fp64", 2, 0)
+    run("mixed", 2, 0)
+    t64, u64, dt64, _ = run("fp64", K, W)
+    tmx, umx, dtmx, _ = run("mixed", K, W)
+    # per-kernel durations: same K steps again, each kernel between HIP events
+    _, _, _, tim = run("mixed", min(K, 50), W, profile=True)
+
+    def wnorm(x):
+        return float(torch.linalg.vector_norm(x))
+
+    err = {}
+    names = ["u_r", "u_theta", "u_z", "T"][:ctx.F]
+    for f, nm in enumerate(names):
+        err[nm] = wnorm(umx[f] - u64[f]) / max(wnorm(u64[f]), 1e-300)
+
+    # dominant kernel and its roofline
+    best = None
+    for kname, (ms, cnt) in tim.items():
+        if cnt == 0 or kname in ("factor", "cfl"):
+            continue
+        if best is None or ms > best[1]:
+            best = (kname, ms, cnt)
+    kname, ms, cnt = best
+    avg_s = ms / cnt / 1e3
+    byt = kernel_bytes(kname, w, "mixed")
+    achieved = byt / avg_s / 1e9
+    per_kernel = {k: {"ms_total": round(v[0], 4), "launches": v[1],
+                      "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None,
+                      "GBps": round(kernel_bytes(k, w, "mixed") / (v[0] / v[1] / 1e3) / 1e9, 1)
+                      if v[1] and kernel_bytes(k, w, "mixed") else None}
+                  for k, v in tim.items()}
+    ctx.close()
+    return dict(K=K, W=W, t64=t64, tmx=tmx, err=err, dt_end=(dt64, dtmx), dominant=kname,
+                avg_us=avg_s * 1e6, bytes=byt, achieved=achieved, per_kernel=per_kernel)
+
+
+def run_cpu(wname, steps):
+    import torch
+
+    import oracle as O
+    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+
+    w = WORKLOADS[wname]
+    p = O.Params(*params(wname))
+    u = O.initial_state(p, amplitudes(wname))
+    dt0 = min(w["dt"], 0.5 * O.cfl_dt(p, u)) if w["dynamic"] else w["dt"]
+    t0 = time.perf_counter()
+    O.run(p, u, steps, dt0=dt0, dynamic=w["dynamic"], cfl=0.5, dt_max=w["dt"])
+    el = time.perf_counter() - t0
+    return dict(value=steps / el, unit="steps/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{steps} FP64 oracle steps of {wname} (dense LU, DFT matrices), "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tc-heated-n64")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a "
+              "design, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    from paper_1908_00587_amd.workloads import WORKLOADS
+    w = WORKLOADS[args.workload]
+    g = run_gpu(args, args.workload)
+    cpu = None if args.no_cpu else run_cpu(args.workload, args.cpu_steps)
+    K = g["K"]
+    mx_sps = K / g["tmx"]
+    fp_sps = K / g["t64"]
+    out = {
+        "metric": METRIC,
+        "value": round(mx_sps, 2),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": g["W"],
+        "ms_per_step": round(1e3 * g["tmx"] / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N_r": w["N_r"], "M_theta": w["M_theta"],
+                   "M_z": w["M_z"], "N_theta": 3 * w["M_theta"],
+                   "N_z": 3 * ((w["M_z"] - 1) // 2 + 1), "Re_i": w["Re_i"], "Ra": w["Ra"],
+                   "dynamic_dt": w["dynamic"], "n_corr": 1, "precision": "mixed",
+                   "parallelism": "single-gpu"},
+        "fp64": {"value": round(fp_sps, 2), "unit": "steps/s",
+                 "ms_per_step": round(1e3 * g["t64"] / K, 4)},
+        "mixed_speedup_vs_fp64": round(mx_sps / fp_sps, 3),
+        "mixed_vs_fp64_rel_err": {k: float(f"{v:.3e}") for k, v in g["err"].items()},
+        "roofline": {"bound": "hbm", "kernel": g["dominant"],
+                     "achieved": round(g["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": g["bytes"], "avg_launch_us": round(g["avg_us"], 3)},
+        "kernels": g["per_kernel"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

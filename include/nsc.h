@@ -1,0 +1,169 @@
+/*
+ * nsc.h -- C ABI of the MI355X Taylor--Couette time-step library (libnsc.so).
+ *
+ * The library advances the incompressible Navier--Stokes equations (and,
+ * optionally, a Boussinesq temperature equation) for the flow between two
+ * independently rotating, differentially heated concentric cylinders, with
+ * the discretisation described in the nsCouette paper (section 2.1,
+ * "Functionality"): Fourier--Galerkin in the azimuthal (theta) and axial (z)
+ * directions with pseudospectral, 3/2-rule dealiased nonlinear terms;
+ * nine-point finite differences in r; a predictor--corrector integrator with
+ * dynamic time-step control; linear terms solved independently per Fourier
+ * mode (section 2.2).  The equations themselves are not printed in the paper;
+ * the library's conventions are:
+ *
+ *   units: gap d = 1, time d^2/nu, velocity nu/d; r_i = eta/(1-eta),
+ *          r_o = 1/(1-eta); Re_i, Re_o = azimuthal wall speeds;
+ *   du/dt = -grad P + lap u + u x omega + Gr T e_z,  Gr = Ra/Pr,
+ *   dT/dt = -u . grad T + lap T / Pr,  T(r_i) = +1/2, T(r_o) = -1/2,
+ *   div u = 0, no slip at both walls, periodic in theta and z.
+ *
+ * ARRAY CONVENTION.  Every spectral array is interleaved complex FP64
+ * (re, im pairs; torch.complex128), contiguous [F][N_r][M_theta][M_z],
+ * F = 3 (u_r, u_theta, u_z) or 4 (+ T) when Ra != 0.  Mode (m, k) has
+ * m = 0..M_theta-1 and k = -K..K, K = (M_z-1)/2, stored at index k+K;
+ * the physical field is f = sum_k f_0k e^{i k kz z}
+ *   + 2 Re sum_{m>=1} sum_k f_mk e^{i(m theta + k kz z)}, kz = 2 pi / L_z,
+ * so the m = 0 column must be Hermitian (f_0,-k = conj f_0,k).  Outputs
+ * are re-symmetrised.  Radial index j = 0..N_r-1 runs from r_i to r_o on
+ * Chebyshev--Gauss--Lobatto points (wall points included).
+ *
+ * OWNERSHIP.  Unless stated otherwise every array pointer is a DEVICE
+ * pointer owned by the caller, at least 16-byte aligned; the library never
+ * frees it nor keeps it after the call returns.  The library owns the
+ * context and all of its workspaces, freed by nsc_destroy.  All device work
+ * is enqueued on the context's stream (nsc_set_stream; default the null
+ * stream) and is asynchronous, except where a call says it synchronises.
+ * A context is not thread-safe: use one context per host thread.
+ *
+ * ERRORS.  Every call returns an int status: NSC_OK or a negative code
+ * (nsc_strerror gives a message).  Arguments are validated before any device
+ * work; a failing call leaves caller arrays untouched when the failure is
+ * detected before launch.
+ */
+#ifndef NSC_H
+#define NSC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nsc_ctx nsc_ctx;
+
+enum {
+  NSC_OK = 0,
+  NSC_ERR_ARG = -1,       /* invalid argument (checked before device work)   */
+  NSC_ERR_DEVICE = -2,    /* HIP runtime error or no device                  */
+  NSC_ERR_OOM = -3,       /* device allocation failed or size overflow       */
+  NSC_ERR_NONFINITE = -4, /* NaN/Inf detected in a reduction                 */
+  NSC_ERR_DT = -5,        /* time step collapsed below 1e-12                 */
+  NSC_ERR_STATE = -6      /* call not valid in the context's current state   */
+};
+
+enum { NSC_FP64 = 0, NSC_MIXED = 1 };
+
+/* Create a context for one problem (Motivation, section 1; section 2.1:
+ * "a single input file defines all relevant parameters ... at runtime").
+ * eta in (0,1); Re_i, Re_o wall speeds; Ra >= 0 (0 = isothermal) and Pr > 0
+ * if Ra != 0; N_r >= 9 radial points; M_theta >= 1 azimuthal modes with
+ * N_theta = 3 M_theta, M_z odd axial modes with N_z = 3 (M_z+1)/2, both
+ * padded lengths of the form 2^a 3^b 5^c and <= 4096; L_z > 0 axial period.
+ * Computes the grid, the finite-difference weights, transform tables and
+ * the Delta t-independent pressure factors, and allocates workspaces.
+ * *out receives the context (NULL on failure).  Errors: NSC_ERR_ARG,
+ * NSC_ERR_DEVICE, NSC_ERR_OOM. */
+int nsc_init(double eta, double Re_i, double Re_o, double Ra, double Pr,
+             int N_r, int M_theta, int M_z, double L_z, nsc_ctx **out);
+
+/* Release the context and every device buffer it owns.  NULL is a no-op. */
+int nsc_destroy(nsc_ctx *ctx);
+
+/* Enqueue all later work on hip_stream (a hipStream_t; NULL = null stream). */
+int nsc_set_stream(nsc_ctx *ctx, void *hip_stream);
+
+/* Precision policy: NSC_FP64 (everything FP64) or NSC_MIXED (transforms and
+ * pointwise products in FP32 with FP32 accumulation; radial solves,
+ * influence correction and reductions stay FP64).  The ABI stays FP64. */
+int nsc_set_precision(nsc_ctx *ctx, int mode);
+
+/* Time integration (section 2.1, predictor--corrector with variable step).
+ * dt > 0 the (initial) step; dynamic = 1 enables CFL control: after each
+ * nsc_step the next step is min(dt_max, cfl * dt_cfl(u^n)), accepted if it
+ * shrinks the step or grows it by more than 10 %; n_corr >= 0 corrector
+ * stages; c_implicit in (0,1] the implicit weight of the viscous term
+ * (0.5 = Crank--Nicolson type).  Defaults: dt = 1e-3, dynamic = 0, cfl = 0.5,
+ * dt_max = 1e-3, n_corr = 1, c = 0.5.  Radial factors are rebuilt lazily
+ * when dt or c changes. */
+int nsc_set_timestep(nsc_ctx *ctx, double dt, int dynamic, double cfl,
+                     double dt_max, int n_corr, double c_implicit);
+
+/* Nonlinear term N(u) (section 2.1 pseudospectral method): curl and
+ * temperature gradient in spectral space, inverse z and theta FFTs onto the
+ * 3/2-padded grid, pointwise u x omega and -u . grad T, forward FFTs,
+ * truncation, buoyancy N_z += Gr T.  u_hat, n_hat: [F][N_r][M_theta][M_z]
+ * (must not alias).  cfl_dt_dev: NULL or one device double receiving
+ * dt_cfl = min over grid points of (dr_j/|u_r|, r_j dtheta/|u_theta|,
+ * dz/|u_z|) (NaN if a non-finite value was met). */
+int nsc_nonlinear(nsc_ctx *ctx, const double *u_hat, double *n_hat,
+                  double *cfl_dt_dev);
+
+/* Implicit stage of the step, per Fourier mode (section 2.2: linear terms
+ * treated independently per mode): with X+- = u_r +- i u_theta,
+ *   f = X^n/dt + (1-c) L X^n + c N^q + (1-c) N^n,
+ *   pressure Poisson with Neumann rows, Helmholtz solves (I/dt - c L) X,
+ *   influence-matrix correction making div u = 0 at both walls,
+ * using the step set by nsc_set_timestep.  u_hat_n, n_hat_n, n_hat_q,
+ * u_hat_out: [F][N_r][M_theta][M_z]; u_hat_out must not alias the inputs.
+ * p_hat_out: NULL or [N_r][M_theta][M_z] pressure head (mode (0,0): the
+ * solution of dp/dr = F_r = c N^q_r + (1-c) N^n_r in divergence form,
+ * (D2 + D1/r) p = (D1 + 1/r) F_r, with p(r_i) = 0 and D1 p = F_r at r_o). */
+int nsc_radial_solve(nsc_ctx *ctx, const double *u_hat_n,
+                     const double *n_hat_n, const double *n_hat_q,
+                     double *u_hat_out, double *p_hat_out);
+
+/* One full time step in place: N^n = N(u^n), predictor X^(1) =
+ * Solve(u^n, N^n, N^n), then n_corr correctors X^(q+1) = Solve(u^n, N^n,
+ * N(X^(q))) (section 2.1).  *dt_inout (HOST pointer): on entry the step
+ * size; on return the size for the next step (changed only if dynamic).
+ * With dynamic control the call waits for the first nonlinear stage's CFL
+ * scalar (the rest of the step stays queued).  Errors: NSC_ERR_NONFINITE,
+ * NSC_ERR_DT. */
+int nsc_step(nsc_ctx *ctx, double *u_hat, double *dt_inout);
+
+/* Perturbation kinetic energy about circular Couette flow,
+ * E = 1/2 int |u - U_b|^2 dV, U_b = (0, A r + B/r, 0), with Clenshaw--Curtis
+ * weights in r and Parseval in theta, z; deterministic FP64 reduction.
+ * e_dev: one device double. */
+int nsc_energy(nsc_ctx *ctx, const double *u_hat, double *e_dev);
+
+/* Divergence-free initial condition exciting selected modes (section 2.1):
+ * amps_dev: [F][M_theta][M_z] complex mode amplitudes (m = 0 column made
+ * Hermitian, mode (0,0) ignored); the perturbation amps * g(r),
+ * g = 16 (r-r_i)^2 (r_o-r)^2, is projected by one backward-Euler Stokes
+ * stage (dt = 1e-3, zero wall data) and added to the basic state (Couette
+ * flow; conduction profile plus the unprojected temperature amplitudes).
+ * Leaves the time-step settings unchanged.  u_hat_out: [F][N_r][M_theta][M_z]. */
+int nsc_initial_state(nsc_ctx *ctx, const double *amps_dev, double *u_hat_out);
+
+/* Radial grid points r_j (HOST array of n >= N_r doubles). */
+int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
+
+/* Per-kernel device time accumulated since the last call, in ms (HOST array
+ * of n doubles), one entry per kernel: [0] z-inverse (curl + inverse z FFT),
+ * [1] theta FFTs + products, [2] forward z FFT, [3] CFL reduction,
+ * [4] right sides, [5] divergence, [6] pressure/temperature sweeps,
+ * [7] velocity sweeps, [8] influence coefficients, [9] finalisation,
+ * [10] factorisation; entries [11..21] the launch counts of the same
+ * kernels.  Counters are reset by the call.  Timing is enabled by
+ * nsc_set_profiling(ctx, 1): each kernel is then bracketed by HIP events on
+ * the context stream and the host waits for the second event. */
+int nsc_get_timings(nsc_ctx *ctx, double *ms, int n);
+int nsc_set_profiling(nsc_ctx *ctx, int on);
+
+/* Static description of the status code. */
+const char *nsc_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSC_H */

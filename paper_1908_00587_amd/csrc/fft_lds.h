@@ -1,0 +1,201 @@
+// LDS-resident mixed-radix FFTs for gfx950 (wave64).
+//
+// Lines of length n live in LDS with a padded stride.  Each stage is a
+// Stockham autosort pass (natural-order in, natural-order out): butterfly j
+// of a stage with accumulated length ns and radix R reads elements
+// j + r n/R, multiplies them by the twiddles w^{r (j mod ns)} with
+// w = e^{-+2 pi i / (ns R)}, applies a length-R DFT and writes to
+// (j / ns) ns R + (j mod ns) + r ns.  All of a thread's butterflies are held
+// in registers between a read phase and a write phase separated by block
+// barriers, so a stage works in place.  Radices 2, 3, 4, 5, 8 cover the
+// padded lengths 3 M_theta and 3 (K+1) of the 3/2-rule grid.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nsc_internal.h"
+
+namespace nsc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by i*s (s = +1 or -1)
+template <typename T>
+__device__ __forceinline__ C2<T> cmul_is(C2<T> a, T s) { return {-s * a.y, s * a.x}; }
+
+// Length-R DFT in registers, y_k = sum_n x_n e^{sgn 2 pi i n k / R},
+// sgn = -1 (forward) or +1 (inverse).
+template <typename T, int R, bool INV>
+struct Dft;
+
+template <typename T, bool INV>
+struct Dft<T, 2, INV> {
+  __device__ __forceinline__ static void run(C2<T> *v) {
+    C2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 3, INV> {
+  __device__ __forceinline__ static void run(C2<T> *v) {
+    const T s = INV ? T(1) : T(-1);
+    const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+    C2<T> a = v[0], b = v[1], c = v[2];
+    C2<T> t1 = cadd(b, c);
+    C2<T> t2 = {a.x - T(0.5) * t1.x, a.y - T(0.5) * t1.y};
+    C2<T> t3 = cmul_is(cscale(csub(b, c), h), s);
+    v[0] = cadd(a, t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 4, INV> {
+  __device__ __forceinline__ static void run(C2<T> *v) {
+    const T s = INV ? T(1) : T(-1);
+    C2<T> a = v[0], b = v[1], c = v[2], d = v[3];
+    C2<T> apc = cadd(a, c), amc = csub(a, c);
+    C2<T> bpd = cadd(b, d), bmd = cmul_is(csub(b, d), s);
+    v[0] = cadd(apc, bpd);
+    v[1] = cadd(amc, bmd);
+    v[2] = csub(apc, bpd);
+    v[3] = csub(amc, bmd);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 5, INV> {
+  __device__ __forceinline__ static void run(C2<T> *v) {
+    const T s = INV ? T(1) : T(-1);
+    const T c1 = T(0.30901699437494742410229341718282);   // cos(2 pi/5)
+    const T c2 = T(-0.80901699437494742410229341718282);  // cos(4 pi/5)
+    const T s1 = T(0.95105651629515357211643933337938);   // sin(2 pi/5)
+    const T s2 = T(0.58778525229247312916870595463907);   // sin(4 pi/5)
+    C2<T> a = v[0];
+    C2<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C2<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    C2<T> r1 = {a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y};
+    C2<T> r2 = {a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y};
+    C2<T> i1 = cmul_is(C2<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, s);
+    C2<T> i2 = cmul_is(C2<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, s);
+    v[0] = cadd(a, cadd(t1, t2));
+    v[1] = cadd(r1, i1);
+    v[4] = csub(r1, i1);
+    v[2] = cadd(r2, i2);
+    v[3] = csub(r2, i2);
+  }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 8, INV> {
+  __device__ __forceinline__ static void run(C2<T> *v) {
+    const T s = INV ? T(1) : T(-1);
+    const T q = T(0.70710678118654752440084436210485);
+    C2<T> e[4] = {v[0], v[2], v[4], v[6]};
+    C2<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<T, 4, INV>::run(e);
+    Dft<T, 4, INV>::run(o);
+    // twiddles w8^k, w8 = e^{s i pi/4}
+    C2<T> o1 = {q * (o[1].x - s * o[1].y), q * (o[1].y + s * o[1].x)};
+    C2<T> o2 = cmul_is(o[2], s);
+    C2<T> o3 = {q * (-o[3].x - s * o[3].y), q * (-o[3].y + s * o[3].x)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// One Stockham stage over `nlines` lines (stride ls) of length n.
+// Requires nlines * n / R <= MAXB * blockDim.x.
+template <typename T, int R, bool INV, int MAXB>
+__device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
+                                          int ns, const C2<T> *__restrict__ tw) {
+  const int nb = n / R;
+  const int total = nlines * nb;
+  const int step = n / (ns * R);
+  C2<T> v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * blockDim.x;
+    if (b < total) {
+      const int line = b / nb;
+      const int j = b - line * nb;
+      const int k = j % ns;
+      const C2<T> *L = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = L[j + r * nb];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C2<T> w = tw[r * k * step];
+        if (INV) w.y = -w.y;
+        v[q][r] = cmul(v[q][r], w);
+      }
+      Dft<T, R, INV>::run(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * blockDim.x;
+    if (b < total) {
+      const int line = b / nb;
+      const int j = b - line * nb;
+      const int k = j % ns;
+      C2<T> *L = buf + line * ls;
+      const int base = (j / ns) * ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) L[base + r * ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of `nlines` LDS lines; forward (e^{-}) or inverse (e^{+}),
+// unnormalised.  tw: n twiddles e^{-2 pi i t / n} in global memory.  Lines
+// are transformed in groups small enough that every stage's butterflies fit
+// MAXB per thread (the host guarantees n / min_radix <= MAXB * blockDim.x).
+template <typename T, bool INV, int MAXB>
+__device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
+                          const C2<T> *__restrict__ tw) {
+  const int n = plan.n;
+  int gl = (MAXB * (int)blockDim.x * plan.min_radix) / n;
+  if (gl < 1) gl = 1;
+  for (int l0 = 0; l0 < nlines; l0 += gl) {
+    const int nl = nlines - l0 < gl ? nlines - l0 : gl;
+    C2<T> *b0 = buf + l0 * ls;
+    int ns = 1;
+    for (int s = 0; s < plan.nst; ++s) {
+      const int R = plan.radix[s];
+      switch (R) {
+        case 2: fft_stage<T, 2, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+        case 3: fft_stage<T, 3, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+        case 4: fft_stage<T, 4, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+        case 5: fft_stage<T, 5, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+        default: fft_stage<T, 8, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+      }
+      ns *= R;
+    }
+  }
+}
+
+}  // namespace nsc

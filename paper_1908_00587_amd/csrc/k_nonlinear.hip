@@ -1,0 +1,380 @@
+// Pseudospectral nonlinear term on gfx950 (section 2.1 of the nsCouette
+// paper: Fourier--Galerkin in theta and z, pseudospectral products).
+//
+// Three passes over HBM:
+//   k_zinv   spectral state [F][N_r][M_theta][M_z] -> derived fields (u,
+//            curl u, grad T) per (r, m) line, zero-padded to N_z, inverse
+//            FFT in z, stored transposed as Z[n_in][N_r][N_z][M_theta]
+//            (theta-lines contiguous);
+//   k_theta  per (r, z) line: pairs of real fields packed into one complex
+//            Hermitian-extended line of length N_theta, inverse FFT, pointwise
+//            u x omega and -u . grad T plus the CFL bound, forward FFT,
+//            unpacking, W[n_out][N_r][N_z][M_theta];
+//   k_zfwd   W -> forward FFT in z, truncation to |k| <= K, scaling
+//            1/(N_theta N_z), buoyancy N_z += Gr T, Hermitian m = 0 column.
+// T = double (FP64) or float (mixed precision); the spectral state and the
+// output stay FP64.
+#include <cfloat>
+#include <climits>
+
+#include "fft_lds.h"
+
+namespace nsc {
+namespace {
+
+constexpr int kMaxB = 4;
+
+// Field `f` of the derived set at (row j, mode m, kk) from the spectral state:
+// 0..2 u_r, u_theta, u_z; 3..5 omega_r, omega_theta, omega_z; 6..8 grad T.
+__device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
+                                           const double2 *__restrict__ u, int f,
+                                           int j, int m, int kk) {
+  const size_t plane = (size_t)d.nmodes;
+  const size_t md = (size_t)m * d.mz + kk;
+  auto U = [&](int fld, int row) -> double2 {
+    return u[((size_t)fld * d.nr + row) * plane + md];
+  };
+  auto D1 = [&](int fld) -> double2 {
+    const int s = g.s[j];
+    const double *w = g.d1 + j * kStencil;
+    double2 acc = {0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kStencil; ++t) {
+      double2 v = U(fld, s + t);
+      acc.x = fma(w[t], v.x, acc.x);
+      acc.y = fma(w[t], v.y, acc.y);
+    }
+    return acc;
+  };
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double mr = (double)m * g.rinv[j];
+  switch (f) {
+    case 0: return U(0, j);
+    case 1: return U(1, j);
+    case 2: return U(2, j);
+    case 3: {  // (i m / r) u_z - i kappa u_theta
+      double2 a = U(2, j), b = U(1, j);
+      double re = mr * a.x - kap * b.x, im = mr * a.y - kap * b.y;
+      return {-im, re};
+    }
+    case 4: {  // i kappa u_r - D1 u_z
+      double2 a = U(0, j), dz = D1(2);
+      return {-kap * a.y - dz.x, kap * a.x - dz.y};
+    }
+    case 5: {  // D1 u_theta + u_theta / r - (i m / r) u_r
+      double2 dt = D1(1), b = U(1, j), a = U(0, j);
+      const double ri = g.rinv[j];
+      return {dt.x + b.x * ri + mr * a.y, dt.y + b.y * ri - mr * a.x};
+    }
+    case 6: return D1(3);
+    case 7: {  // (i m / r) T
+      double2 a = U(3, j);
+      return {-mr * a.y, mr * a.x};
+    }
+    default: {  // i kappa T
+      double2 a = U(3, j);
+      return {-kap * a.y, kap * a.x};
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
+                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  const int nz = d.nz, K = d.kmax;
+  const int ls = nz + 1;
+  const int mt0 = blockIdx.x * tm;
+  const int j = blockIdx.y;
+  const int f = blockIdx.z;
+  const int nl = min(tm, d.mt - mt0);
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int li = idx / nz;
+    const int b = idx - li * nz;
+    C2<T> val = {T(0), T(0)};
+    int k = INT_MIN;
+    if (b <= K) k = b;
+    else if (b >= nz - K) k = b - nz;
+    if (k != INT_MIN) {
+      double2 v = derived(d, g, u, f, j, mt0 + li, k + K);
+      val = {T(v.x), T(v.y)};
+    }
+    buf[li * ls + b] = val;
+  }
+  __syncthreads();
+  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tw);
+  C2<T> *out = Z + ((size_t)f * d.nr + j) * nz * d.mt;
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int b = idx / nl;
+    const int li = idx - b * nl;
+    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + b];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> ldz(const C2<T> *__restrict__ p) { return *p; }
+
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
+                        C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
+                        double dth, double dzs, double *__restrict__ cfl_part,
+                        int want_cfl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  __shared__ double red[kFftThreads / 64];
+  const int nt = d.nt, mt = d.mt;
+  const int ls = nt + 1;
+  const int b = blockIdx.x;  // z index
+  const int j = blockIdx.y;  // radial row
+  const int npi = (n_in + 1) / 2;
+  const size_t fstride = (size_t)d.nr * d.nz * mt;
+  const C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
+  // pack pairs of real fields into Hermitian-extended complex lines
+  for (int idx = threadIdx.x; idx < npi * nt; idx += blockDim.x) {
+    const int p = idx / nt;
+    const int a = idx - p * nt;
+    const int f1 = 2 * p, f2 = 2 * p + 1;
+    C2<T> v = {T(0), T(0)};
+    if (a == 0) {
+      C2<T> F1 = zl[f1 * fstride];
+      C2<T> F2 = f2 < n_in ? zl[f2 * fstride] : C2<T>{T(0), T(0)};
+      v = {F1.x, F2.x};
+    } else if (a < mt) {
+      C2<T> F1 = zl[f1 * fstride + a];
+      C2<T> F2 = f2 < n_in ? zl[f2 * fstride + a] : C2<T>{T(0), T(0)};
+      v = {F1.x - F2.y, F1.y + F2.x};
+    } else if (a > nt - mt) {
+      const int m = nt - a;
+      C2<T> F1 = zl[f1 * fstride + m];
+      C2<T> F2 = f2 < n_in ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
+      v = {F1.x + F2.y, F2.x - F1.y};
+    }
+    buf[p * ls + a] = v;
+  }
+  __syncthreads();
+  fft_lines<T, true, kMaxB>(buf, npi, ls, pt, tw);
+  // pointwise products and CFL bound
+  const double rj = g.r[j], drj = g.dr[j];
+  double lmin = DBL_MAX;
+  bool bad = false;
+  const bool heated = n_in > 6;
+  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
+    C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
+    const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
+    const T nr_ = ut * wz - uz * wt;
+    const T nth = uz * wr - ur * wz;
+    const T nzz = ur * wt - ut * wr;
+    T ntt = T(0);
+    if (heated) {
+      C2<T> l3 = buf[3 * ls + a], l4 = buf[4 * ls + a];
+      ntt = -(ur * l3.x + ut * l3.y + uz * l4.x);
+    }
+    buf[a] = {nr_, nth};
+    buf[ls + a] = {nzz, ntt};
+    if (want_cfl) {
+      const double aur = fabs((double)ur), aut = fabs((double)ut), auz = fabs((double)uz);
+      if (!(isfinite(aur) && isfinite(aut) && isfinite(auz))) bad = true;
+      if (aur > 0.0) lmin = fmin(lmin, drj / aur);
+      if (aut > 0.0) lmin = fmin(lmin, rj * dth / aut);
+      if (auz > 0.0) lmin = fmin(lmin, dzs / auz);
+    }
+  }
+  __syncthreads();
+  fft_lines<T, false, kMaxB>(buf, 2, ls, pt, tw);
+  // unpack the two real transforms of each line, keep m < M_theta
+  const int nout = heated ? 4 : 3;
+  C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
+  for (int idx = threadIdx.x; idx < 2 * mt; idx += blockDim.x) {
+    const int p = idx / mt;
+    const int m = idx - p * mt;
+    const C2<T> zm = buf[p * ls + m];
+    const C2<T> zc = buf[p * ls + (m == 0 ? 0 : nt - m)];
+    // X = (Z_m + conj Z_{-m}) / 2, Y = (Z_m - conj Z_{-m}) / (2 i)
+    const C2<T> x = {T(0.5) * (zm.x + zc.x), T(0.5) * (zm.y - zc.y)};
+    const C2<T> y = {T(0.5) * (zm.y + zc.y), T(0.5) * (zc.x - zm.x)};
+    wl[(size_t)(2 * p) * fstride + m] = x;
+    if (2 * p + 1 < nout) wl[(size_t)(2 * p + 1) * fstride + m] = y;
+  }
+  if (want_cfl) {
+    if (bad) lmin = NAN;
+    // wave reduction then block reduction (min, NaN-propagating)
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(lmin, off, 64);
+      lmin = (isnan(o) || isnan(lmin)) ? NAN : fmin(lmin, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = lmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = red[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        v = (isnan(v) || isnan(red[w])) ? NAN : fmin(v, red[w]);
+      cfl_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, FftPlan pz, const C2<T> *__restrict__ W,
+                       const double2 *__restrict__ u, double2 *__restrict__ nh,
+                       const C2<T> *__restrict__ tw, int tm, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  const int nz = d.nz, K = d.kmax, mz = d.mz;
+  const int ls = nz + 1;
+  const int mt0 = blockIdx.x * tm;
+  const int j = blockIdx.y;
+  const int f = blockIdx.z;
+  const int nl = min(tm, d.mt - mt0);
+  const C2<T> *in = W + ((size_t)f * d.nr + j) * nz * d.mt;
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int b = idx / nl;
+    const int li = idx - b * nl;
+    buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
+  }
+  __syncthreads();
+  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tw);
+  const size_t plane = (size_t)d.nmodes;
+  const bool buoy = (f == 2) && d.heated;
+  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
+    const int li = idx / mz;
+    const int kk = idx - li * mz;
+    const int m = mt0 + li;
+    const int k = kk - K;
+    const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
+    double2 o = {(double)v.x * scale, (double)v.y * scale};
+    const size_t md = (size_t)m * mz + kk;
+    if (buoy) {
+      const double2 t = u[((size_t)3 * d.nr + j) * plane + md];
+      o.x += d.gr * t.x;
+      o.y += d.gr * t.y;
+    }
+    if (m == 0) {
+      const int kkm = mz - 1 - kk;
+      const C2<T> vm = buf[li * ls + (k <= 0 ? -k : nz - k)];
+      double2 om = {(double)vm.x * scale, (double)vm.y * scale};
+      if (buoy) {
+        const double2 t = u[((size_t)3 * d.nr + j) * plane + kkm];
+        om.x += d.gr * t.x;
+        om.y += d.gr * t.y;
+      }
+      o = {0.5 * (o.x + om.x), 0.5 * (o.y - om.y)};
+    }
+    nh[((size_t)f * d.nr + j) * plane + md] = o;
+  }
+}
+
+__global__ void k_cfl_final(const double *__restrict__ part, int n, double *out) {
+  __shared__ double red[16];
+  double v = DBL_MAX;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double p = part[i];
+    v = (isnan(v) || isnan(p)) ? NAN : fmin(v, p);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_down(v, off, 64);
+    v = (isnan(o) || isnan(v)) ? NAN : fmin(v, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      r = (isnan(r) || isnan(red[w])) ? NAN : fmin(r, red[w]);
+    out[0] = r;
+  }
+}
+
+int min_radix(const FftPlan &p) { return p.min_radix; }
+
+// Threads so that nlines * n / min_radix butterflies fit kMaxB per thread,
+// capped at the FFT kernels' launch bound (then lines go in groups).
+int block_for(const FftPlan &p, int nlines, int floor_threads) {
+  const int bf = nlines * p.n / min_radix(p);
+  int t = (bf + kMaxB - 1) / kMaxB;
+  t = ((t + 63) / 64) * 64;
+  if (t < floor_threads) t = floor_threads;
+  if (t > kFftThreads) t = kFftThreads;
+  return t;
+}
+
+// Lines per block for the z passes: LDS budget and butterfly budget.
+int z_lines(const nsc_ctx *c, size_t esize) {
+  const size_t budget = 64 * 1024;
+  int tm = (int)(budget / ((size_t)(c->d.nz + 1) * esize));
+  const int bf_cap = kMaxB * kFftThreads * min_radix(c->plan_z) / c->d.nz;
+  if (tm > bf_cap) tm = bf_cap;
+  if (tm > 16) tm = 16;
+  if (tm > c->d.mt) tm = c->d.mt;
+  if (tm < 1) tm = 1;
+  return tm;
+}
+
+template <typename T>
+hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
+  const int tm = z_lines(c, sizeof(C2<T>));
+  dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
+  const int threads = block_for(c->plan_z, tm, 256);
+  const size_t shm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  hipLaunchKernelGGL(k_zinv<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
+                     c->plan_z, reinterpret_cast<const double2 *>(u),
+                     reinterpret_cast<C2<T> *>(c->zbuf),
+                     reinterpret_cast<const C2<T> *>(tw), tm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
+  dim3 grid(c->d.nz, c->d.nr);
+  const int npi = (c->n_in + 1) / 2;
+  const int threads = block_for(c->plan_t, npi, 256);
+  const size_t shm = (size_t)npi * (c->d.nt + 1) * sizeof(C2<T>);
+  const double dth = 2.0 * M_PI / c->d.nt;
+  const double dzs = c->d.lz / c->d.nz;
+  hipLaunchKernelGGL(k_theta<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
+                     c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
+                     reinterpret_cast<C2<T> *>(c->wbuf),
+                     reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
+                     c->cfl_part, want_cfl);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw) {
+  const int tm = z_lines(c, sizeof(C2<T>));
+  dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
+  const int threads = block_for(c->plan_z, tm, 256);
+  const size_t shm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
+  hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->plan_z,
+                     reinterpret_cast<const C2<T> *>(c->wbuf),
+                     reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
+                     reinterpret_cast<const C2<T> *>(tw), tm, scale);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u) {
+  if (prec == NSC_MIXED) return zinv_impl<float>(c, u, c->tw32_z);
+  return zinv_impl<double>(c, u, c->tw64_z);
+}
+
+hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl) {
+  if (prec == NSC_MIXED) return theta_impl<float>(c, c->tw32_t, want_cfl);
+  return theta_impl<double>(c, c->tw64_t, want_cfl);
+}
+
+hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat) {
+  if (prec == NSC_MIXED) return zfwd_impl<float>(c, u, n_hat, c->tw32_z);
+  return zfwd_impl<double>(c, u, n_hat, c->tw64_z);
+}
+
+hipError_t launch_cfl_final(const nsc_ctx *c, double *out) {
+  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, c->stream, c->cfl_part,
+                     c->cfl_nblk, out);
+  return hipGetLastError();
+}
+
+}  // namespace nsc

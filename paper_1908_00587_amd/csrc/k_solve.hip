@@ -1,0 +1,761 @@
+// Per-Fourier-mode radial solves on gfx950 (section 2.2 of the nsCouette
+// paper: the linear terms are independent per mode).  All FP64.
+//
+// Operators (q = azimuthal order of the family, kappa = k kz):
+//   L_q = D2 + R^-1 D1 - q^2 R^-2 - kappa^2 I  (nine-point rows)
+//   Helmholtz  H = alpha I - beta L_q, identity (Dirichlet) wall rows;
+//   Poisson    L_q with D1 (Neumann) wall rows;
+//   mean head  (D2 + D1/r) rows, p(r_i) = 0 in row 0, D1 row at r_o.
+// Factors: LU without pivoting (growth factor < 1 on these operators), kept
+// in the matrix envelope: row j stores L_{j,j-4..j-1}, 1/U_jj, U_{j,j+1..j+4}
+// plus the wider one-sided rows 0..3 (U up to column 8) and N-4..N-1 (L from
+// column N-9).  One thread per operator (factor) or per mode (solve); modes
+// are laid out so that a wavefront's lanes read consecutive addresses.
+#include <cfloat>
+
+#include "nsc_internal.h"
+
+namespace nsc {
+namespace {
+
+__device__ __forceinline__ int edge_off(int t) { return t * 4 - (t * (t - 1)) / 2; }
+
+struct Cd {
+  double x, y;
+};
+__device__ __forceinline__ Cd operator+(Cd a, Cd b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Cd operator-(Cd a, Cd b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ Cd operator*(double s, Cd a) { return {s * a.x, s * a.y}; }
+__device__ __forceinline__ Cd ci(Cd a) { return {-a.y, a.x}; }  // i * a
+__device__ __forceinline__ Cd ld(const double2 *p) {
+  double2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st(double2 *p, Cd v) { *p = make_double2(v.x, v.y); }
+__device__ __forceinline__ Cd fmac(double w, Cd v, Cd acc) { return {fma(w, v.x, acc.x), fma(w, v.y, acc.y)}; }
+
+// Matrix entry A[i][c] of an operator for c in the window of row i.
+struct OpRow {
+  int kind;
+  double alpha, beta, q2, k2;
+  __device__ __forceinline__ void row(const Grid &g, int n, int i, double *a, int &s) const {
+    s = g.s[i];
+    const double *w1 = g.d1 + i * kStencil;
+    const double *w2 = g.d2 + i * kStencil;
+    const double ri = g.rinv[i];
+    if (kind == OP_HELMHOLTZ) {
+      if (i == 0 || i == n - 1) {
+#pragma unroll
+        for (int t = 0; t < kStencil; ++t) a[t] = (s + t == i) ? 1.0 : 0.0;
+        return;
+      }
+#pragma unroll
+      for (int t = 0; t < kStencil; ++t) {
+        double v = -beta * (w2[t] + w1[t] * ri);
+        if (s + t == i) v += alpha + beta * (q2 * ri * ri + k2);
+        a[t] = v;
+      }
+    } else if (kind == OP_POISSON) {
+      if (i == 0 || i == n - 1) {
+#pragma unroll
+        for (int t = 0; t < kStencil; ++t) a[t] = w1[t];
+        return;
+      }
+#pragma unroll
+      for (int t = 0; t < kStencil; ++t) {
+        double v = w2[t] + w1[t] * ri;
+        if (s + t == i) v -= q2 * ri * ri + k2;
+        a[t] = v;
+      }
+    } else {  // mean pressure head: (D2 + D1/r) p inside, p(r_i) = 0, D1 row at r_o
+      if (i == 0) {
+#pragma unroll
+        for (int t = 0; t < kStencil; ++t) a[t] = (s + t == 0) ? 1.0 : 0.0;
+        return;
+      }
+      if (i == n - 1) {
+#pragma unroll
+        for (int t = 0; t < kStencil; ++t) a[t] = w1[t];
+        return;
+      }
+#pragma unroll
+      for (int t = 0; t < kStencil; ++t) a[t] = w2[t] + w1[t] * ri;
+    }
+  }
+};
+
+constexpr int kBW = 17;  // band window width: columns i-8 .. i+8
+constexpr int kFacThreads = 32;
+
+// One thread per operator: op = q*(K+1) + |k|.  Band elimination without
+// pivoting over a sliding 9-row window held in LDS.
+__global__ void __launch_bounds__(kFacThreads)
+k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_off) {
+  __shared__ double win[9 * kBW * kFacThreads];
+  const int tid = threadIdx.x;
+  const int op = blockIdx.x * kFacThreads + tid;
+  if (op >= F.nops) return;
+  auto W = [&](int ring, int bi) -> double & { return win[(ring * kBW + bi) * kFacThreads + tid]; };
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int q = op / kp1 + q_off;
+  const int ka = op - (op / kp1) * kp1;
+  const double kap = (double)ka * d.kz;
+  OpRow R{kind, alpha, beta, (double)q * (double)q, kap * kap};
+  const size_t nops = F.nops;
+  // singular pure-Neumann operator (q = 0, kappa = 0): not used
+  if (kind == OP_POISSON && q == 0 && ka == 0) {
+    for (int j = 0; j < n; ++j)
+      for (int sl = 0; sl < kSlots; ++sl) F.vals[((size_t)j * kSlots + sl) * nops + op] = 0.0;
+    for (int e = 0; e < kEdge; ++e) F.edge[(size_t)e * nops + op] = 0.0;
+    return;
+  }
+  auto load_row = [&](int i) {
+    const int ring = i % 9;
+    for (int bi = 0; bi < kBW; ++bi) W(ring, bi) = 0.0;
+    double a[kStencil];
+    int s;
+    R.row(g, n, i, a, s);
+    for (int t = 0; t < kStencil; ++t) W(ring, s + t - i + 8) = a[t];
+  };
+  const int first = n < 9 ? n : 9;
+  for (int i = 0; i < first; ++i) load_row(i);
+  for (int k = 0; k < n; ++k) {
+    const int rk = k % 9;
+    const double dinv = 1.0 / W(rk, 8);
+    const int last = min(k + 8, n - 1);
+    for (int i = k + 1; i <= last; ++i) {
+      const int ri = i % 9;
+      const double l = W(ri, k - i + 8) * dinv;
+      W(ri, k - i + 8) = l;
+      if (l != 0.0)
+        for (int c = k + 1; c <= last; ++c) W(ri, c - i + 8) -= l * W(rk, c - k + 8);
+    }
+    // row k is final
+    double *v = F.vals + (size_t)k * kSlots * nops + op;
+    for (int t = 1; t <= 4; ++t) {
+      const int c = k - t;
+      v[(size_t)(4 - t) * nops] = c >= 0 ? W(rk, c - k + 8) : 0.0;
+      const int cu = k + t;
+      v[(size_t)(4 + t) * nops] = cu < n ? W(rk, cu - k + 8) : 0.0;
+    }
+    v[(size_t)4 * nops] = dinv;
+    if (k <= 3)
+      for (int c = k + 5; c <= 8 && c < n; ++c)
+        F.edge[(size_t)(edge_off(k) + c - (k + 5)) * nops + op] = W(rk, c - k + 8);
+    if (k >= n - 4) {
+      const int t = n - 1 - k;
+      for (int c = n - 9; c <= k - 5; ++c)
+        if (c >= 0) F.edge[(size_t)(10 + edge_off(t) + c - (n - 9)) * nops + op] = W(rk, c - k + 8);
+    }
+    if (k + 9 < n) load_row(k + 9);
+  }
+}
+
+// Forward/back substitution for one lane.  RHS(j) gives b_j, OUT(j) the
+// storage for y_j then x_j (global, read back by the same lane).
+template <typename V, typename RHS, typename OUT>
+__device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rhs, OUT out) {
+  const size_t nops = F.nops;
+  const double *vals = F.vals + op;
+  const double *edge = F.edge + op;
+  V yb[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) yb[t] = V{};
+  for (int j = 0; j < n; ++j) {
+    V y = rhs(j);
+    const double *v = vals + (size_t)j * kSlots * nops;
+#pragma unroll
+    for (int t = 1; t <= 4; ++t)
+      if (j - t >= 0) y = y - v[(size_t)(4 - t) * nops] * yb[t - 1];
+    if (j >= n - 4) {
+      const int tt = n - 1 - j;
+#pragma unroll
+      for (int b = 5; b <= 8; ++b) {
+        const int c = j - b;
+        if (c >= n - 9 && c >= 0) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * yb[b - 1];
+      }
+    }
+#pragma unroll
+    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
+    yb[0] = y;
+    out(j) = y;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) yb[t] = V{};
+  for (int j = n - 1; j >= 0; --j) {
+    V x = out(j);
+    const double *v = vals + (size_t)j * kSlots * nops;
+#pragma unroll
+    for (int t = 1; t <= 4; ++t)
+      if (j + t < n) x = x - v[(size_t)(4 + t) * nops] * yb[t - 1];
+    if (j <= 3) {
+#pragma unroll
+      for (int b = 5; b <= 8; ++b) {
+        const int c = j + b;
+        if (c <= 8 && c < n) x = x - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * yb[b - 1];
+      }
+    }
+    x = v[(size_t)4 * nops] * x;
+#pragma unroll
+    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
+    yb[0] = x;
+    out(j) = x;
+  }
+}
+
+struct Rd {
+  double v;
+};
+__device__ __forceinline__ Rd operator-(Rd a, Rd b) { return {a.v - b.v}; }
+__device__ __forceinline__ Rd operator*(double s, Rd a) { return {s * a.v}; }
+
+__device__ __forceinline__ double d1_row(const Grid &g, int j, const double *x, size_t stride) {
+  const int s = g.s[j];
+  const double *w = g.d1 + j * kStencil;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < kStencil; ++t) acc = fma(w[t], x[(size_t)(s + t) * stride], acc);
+  return acc;
+}
+
+__device__ __forceinline__ Cd d1_rowc(const Grid &g, int j, const double2 *x, size_t stride) {
+  const int s = g.s[j];
+  const double *w = g.d1 + j * kStencil;
+  Cd acc = {0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kStencil; ++t) acc = fmac(w[t], ld(x + (size_t)(s + t) * stride), acc);
+  return acc;
+}
+
+// Homogeneous responses and inverse influence matrices per (m, |k|).
+__global__ void __launch_bounds__(64) k_influence_setup(Dims d, Grid g, Factors fp, Factors fv, Influence I) {
+  const int op = blockIdx.x * blockDim.x + threadIdx.x;
+  if (op >= I.nops) return;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = op / kp1;
+  const int ka = op - m * kp1;
+  const size_t ns = I.nops;
+  double *P1 = I.resp + 0 * (size_t)n * ns + op;
+  double *P2 = I.resp + 1 * (size_t)n * ns + op;
+  double *Xp1 = I.resp + 2 * (size_t)n * ns + op;
+  double *Xp2 = I.resp + 3 * (size_t)n * ns + op;
+  double *Xm1 = I.resp + 4 * (size_t)n * ns + op;
+  double *Xm2 = I.resp + 5 * (size_t)n * ns + op;
+  double *H1 = I.resp + 6 * (size_t)n * ns + op;
+  double *H2 = I.resp + 7 * (size_t)n * ns + op;
+  if (m == 0 && ka == 0) {
+    for (int s = 0; s < 8; ++s)
+      for (int j = 0; j < n; ++j) I.resp[((size_t)s * n + j) * ns + op] = 0.0;
+    for (int e = 0; e < 4; ++e) I.ainv[(size_t)e * ns + op] = 0.0;
+    return;
+  }
+  const double mm = (double)m;
+  const int op_p = m * kp1 + ka;
+  const int op_plus = (m + 1) * kp1 + ka;
+  const int op_minus = (m >= 1 ? m - 1 : 1 - m) * kp1 + ka;
+  const int op_z = m * kp1 + ka;
+  // p_j: Neumann data e_0 / e_{N-1}
+  lu_solve<Rd>(fp, op_p, n, [&](int j) { return Rd{j == 0 ? 1.0 : 0.0}; },
+               [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&P1[(size_t)j * ns]); });
+  lu_solve<Rd>(fp, op_p, n, [&](int j) { return Rd{j == n - 1 ? 1.0 : 0.0}; },
+               [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&P2[(size_t)j * ns]); });
+  for (int jj = 0; jj < 2; ++jj) {
+    const double *Pj = jj == 0 ? P1 : P2;
+    double *Xp = jj == 0 ? Xp1 : Xp2;
+    double *Xm = jj == 0 ? Xm1 : Xm2;
+    double *Hh = jj == 0 ? H1 : H2;
+    // X+ = H_{m+1}^-1 (-(D1 p - m p / r)), X- = H_{|m-1|}^-1 (-(D1 p + m p / r))
+    lu_solve<Rd>(fv, op_plus, n,
+                 [&](int j) {
+                   if (j == 0 || j == n - 1) return Rd{0.0};
+                   const double dp = d1_row(g, j, Pj, ns);
+                   return Rd{-(dp - mm * g.rinv[j] * Pj[(size_t)j * ns])};
+                 },
+                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Xp[(size_t)j * ns]); });
+    lu_solve<Rd>(fv, op_minus, n,
+                 [&](int j) {
+                   if (j == 0 || j == n - 1) return Rd{0.0};
+                   const double dp = d1_row(g, j, Pj, ns);
+                   return Rd{-(dp + mm * g.rinv[j] * Pj[(size_t)j * ns])};
+                 },
+                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Xm[(size_t)j * ns]); });
+    // h = H_m^-1 p, so that X_z = -i kappa h
+    lu_solve<Rd>(fv, op_z, n,
+                 [&](int j) {
+                   if (j == 0 || j == n - 1) return Rd{0.0};
+                   return Rd{Pj[(size_t)j * ns]};
+                 },
+                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Hh[(size_t)j * ns]); });
+  }
+  // A[w][jj] = wall divergence of response jj (walls carry zero velocity)
+  double A[2][2];
+  for (int jj = 0; jj < 2; ++jj) {
+    const double *Xp = jj == 0 ? Xp1 : Xp2;
+    const double *Xm = jj == 0 ? Xm1 : Xm2;
+    for (int w = 0; w < 2; ++w) {
+      const int j = w == 0 ? 0 : n - 1;
+      const double ri = g.rinv[j];
+      A[w][jj] = 0.5 * ((d1_row(g, j, Xp, ns) + (1.0 + mm) * ri * Xp[(size_t)j * ns]) +
+                        (d1_row(g, j, Xm, ns) + (1.0 - mm) * ri * Xm[(size_t)j * ns]));
+    }
+  }
+  const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+  I.ainv[0 * ns + op] = A[1][1] / det;
+  I.ainv[1 * ns + op] = -A[0][1] / det;
+  I.ainv[2 * ns + op] = -A[1][0] / det;
+  I.ainv[3 * ns + op] = A[0][0] / det;
+}
+
+// f_X = X^n/dt + (1-c) L_q X^n + c N^q + (1-c) N^n for X in {+, -, z, T}.
+__global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__restrict__ u,
+                      const double2 *__restrict__ nn, const double2 *__restrict__ nq,
+                      double2 *__restrict__ sf, double idt, double cc) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double ri = g.rinv[j];
+  const int s = g.s[j];
+  const double *w1 = g.d1 + j * kStencil;
+  const double *w2 = g.d2 + j * kStencil;
+  const double ce = 1.0 - cc;
+  auto U = [&](int f, int row) { return ld(u + ((size_t)f * n + row) * P + md); };
+  // stencil sums of (D2 + D1/r) applied to u_r, u_theta, u_z (and T)
+  Cd lr = {0, 0}, lt = {0, 0}, lz = {0, 0}, lT = {0, 0};
+#pragma unroll
+  for (int t = 0; t < kStencil; ++t) {
+    const double w = w2[t] + w1[t] * ri;
+    lr = fmac(w, U(0, s + t), lr);
+    lt = fmac(w, U(1, s + t), lt);
+    lz = fmac(w, U(2, s + t), lz);
+    if (d.heated) lT = fmac(w, U(3, s + t), lT);
+  }
+  const Cd ur = U(0, j), ut = U(1, j), uz = U(2, j);
+  const Cd xp = ur + ci(ut), xm = ur - ci(ut);
+  const Cd lp = lr + ci(lt), lm = lr - ci(lt);
+  const double qp = (double)(m + 1), qm = (double)(m >= 1 ? m - 1 : 1 - m), qz = (double)m;
+  const double k2 = kap * kap, r2 = ri * ri;
+  const Cd Lp = lp - (qp * qp * r2 + k2) * xp;
+  const Cd Lm = lm - (qm * qm * r2 + k2) * xm;
+  const Cd Lz = lz - (qz * qz * r2 + k2) * uz;
+  Cd np = {0, 0}, nmn = {0, 0}, nz = {0, 0}, nT = {0, 0};
+  if (nn) {
+    const Cd a = ld(nn + ((size_t)0 * n + j) * P + md), b = ld(nn + ((size_t)1 * n + j) * P + md);
+    const Cd a2 = ld(nq + ((size_t)0 * n + j) * P + md), b2 = ld(nq + ((size_t)1 * n + j) * P + md);
+    np = cc * (a2 + ci(b2)) + ce * (a + ci(b));
+    nmn = cc * (a2 - ci(b2)) + ce * (a - ci(b));
+    nz = cc * ld(nq + ((size_t)2 * n + j) * P + md) + ce * ld(nn + ((size_t)2 * n + j) * P + md);
+    if (d.heated)
+      nT = cc * ld(nq + ((size_t)3 * n + j) * P + md) + ce * ld(nn + ((size_t)3 * n + j) * P + md);
+  }
+  st(sf + ((size_t)0 * n + j) * P + md, idt * xp + ce * Lp + np);
+  st(sf + ((size_t)1 * n + j) * P + md, idt * xm + ce * Lm + nmn);
+  st(sf + ((size_t)2 * n + j) * P + md, idt * uz + ce * Lz + nz);
+  if (d.heated) {
+    const Cd T = U(3, j);
+    const Cd LT = lT - (qz * qz * r2 + k2) * T;
+    st(sf + ((size_t)3 * n + j) * P + md, idt * T + (ce / d.pr) * LT + nT);
+  }
+}
+
+// g = 1/2 [(D1 + (1+m)/r) f+ + (D1 + (1-m)/r) f-] + i kappa f_z; zero wall rows.
+__global__ void k_div(Dims d, Grid g, const double2 *__restrict__ sf, double2 *__restrict__ sg) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  if (j == 0 || j == n - 1) {
+    st(sg + (size_t)j * P + md, Cd{0, 0});
+    return;
+  }
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double ri = g.rinv[j];
+  const double2 *fp = sf + md, *fm = sf + (size_t)n * P + md, *fz = sf + (size_t)2 * n * P + md;
+  const Cd dp = d1_rowc(g, j, fp, P), dm = d1_rowc(g, j, fm, P);
+  const Cd vp = ld(fp + (size_t)j * P), vm = ld(fm + (size_t)j * P), vz = ld(fz + (size_t)j * P);
+  const Cd gval = 0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz);
+  st(sg + (size_t)j * P + md, gval);
+}
+
+// sys 0: pressure p0 (mode (0,0): mean head if requested); sys 1: temperature.
+__global__ void __launch_bounds__(256) k_solve_pt(Dims d, Grid g, Factors fp, Factors fp00, Factors ft,
+                           const double2 *__restrict__ sg, const double2 *__restrict__ sf,
+                           const double2 *__restrict__ nn, const double2 *__restrict__ nq,
+                           double2 *__restrict__ sp, double2 *__restrict__ sT, double cc,
+                           int walls, int want_p) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const int sys = blockIdx.y;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  const bool zero = (m == 0 && ka == 0);
+  auto out_p = [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(sp + (size_t)j * P + md); };
+  if (sys == 0) {
+    if (zero) {
+      if (want_p && nn) {
+        // dp/dr = F_r in divergence form: rhs (D1 + 1/r) F_r, F_r(r_o) at the wall
+        auto Fr = [&](int t) {
+          return cc * ld(nq + (size_t)t * P + md) + (1.0 - cc) * ld(nn + (size_t)t * P + md);
+        };
+        lu_solve<Cd>(fp00, 0, n,
+                     [&](int j) {
+                       if (j == 0) return Cd{0, 0};
+                       if (j == n - 1) return Fr(n - 1);
+                       const int s0 = g.s[j];
+                       const double *w = g.d1 + j * kStencil;
+                       Cd acc = g.rinv[j] * Fr(j);
+                       for (int t = 0; t < kStencil; ++t) acc = fmac(w[t], Fr(s0 + t), acc);
+                       return acc;
+                     },
+                     out_p);
+      } else {
+        for (int j = 0; j < n; ++j) out_p(j) = Cd{0, 0};
+      }
+      return;
+    }
+    lu_solve<Cd>(fp, m * kp1 + ka, n, [&](int j) { return ld(sg + (size_t)j * P + md); }, out_p);
+  } else {
+    const double2 *fT = sf + (size_t)3 * n * P + md;
+    const Cd w0 = (zero && walls) ? Cd{0.5, 0} : Cd{0, 0};
+    const Cd w1 = (zero && walls) ? Cd{-0.5, 0} : Cd{0, 0};
+    lu_solve<Cd>(ft, m * kp1 + ka, n,
+                 [&](int j) {
+                   if (j == 0) return w0;
+                   if (j == n - 1) return w1;
+                   return ld(fT + (size_t)j * P);
+                 },
+                 [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(sT + (size_t)j * P + md); });
+  }
+}
+
+// comp 0: X0+, 1: X0-, 2: X0z.
+__global__ void __launch_bounds__(256) k_solve_vel(Dims d, Grid g, Factors fv, const double2 *__restrict__ sf,
+                            const double2 *__restrict__ sp, double2 *__restrict__ sx, int walls) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const int comp = blockIdx.y;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const bool zero = (m == 0 && ka == 0);
+  const int q = comp == 0 ? m + 1 : (comp == 1 ? (m >= 1 ? m - 1 : 1 - m) : m);
+  const double2 *f = sf + (size_t)comp * n * P + md;
+  const double2 *fp = sf + md, *fm = sf + (size_t)n * P + md;
+  const double2 *p = sp + md;
+  double2 *out = sx + (size_t)comp * n * P + md;
+  const double mm = (double)m;
+  Cd w0 = {0, 0}, w1 = {0, 0};
+  if (zero && walls && comp < 2) {
+    const double sgn = comp == 0 ? 1.0 : -1.0;  // X+- = +-i u_theta
+    w0 = {0.0, sgn * d.re_i};
+    w1 = {0.0, sgn * d.re_o};
+  }
+  auto rhs = [&](int j) -> Cd {
+    if (j == 0) return w0;
+    if (j == n - 1) return w1;
+    if (zero) {
+      if (comp == 2) return ld(f + (size_t)j * P);
+      const Cd h = 0.5 * (ld(fp + (size_t)j * P) - ld(fm + (size_t)j * P));
+      return comp == 0 ? h : Cd{-h.x, -h.y};
+    }
+    const Cd pj = ld(p + (size_t)j * P);
+    Cd gp;
+    if (comp == 2) {
+      gp = kap * ci(pj);
+    } else {
+      const Cd dp = d1_rowc(g, j, p, P);
+      const double mr = mm * g.rinv[j];
+      gp = comp == 0 ? dp - mr * pj : dp + mr * pj;
+    }
+    return ld(f + (size_t)j * P) - gp;
+  };
+  lu_solve<Cd>(fv, q * kp1 + ka, n, rhs,
+               [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(out + (size_t)j * P); });
+}
+
+// lambda = -A^-1 beta(X0), beta = divergence at the two walls.
+__global__ void k_influence(Dims d, Grid g, Influence I, const double2 *__restrict__ sx,
+                            double2 *__restrict__ lam) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  if (m == 0 && ka == 0) {
+    st(lam + 2 * (size_t)md, Cd{0, 0});
+    st(lam + 2 * (size_t)md + 1, Cd{0, 0});
+    return;
+  }
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double mm = (double)m;
+  const double2 *xp = sx + md, *xm = sx + (size_t)n * P + md, *xz = sx + (size_t)2 * n * P + md;
+  Cd beta[2];
+  for (int w = 0; w < 2; ++w) {
+    const int j = w == 0 ? 0 : n - 1;
+    const double ri = g.rinv[j];
+    beta[w] = 0.5 * ((d1_rowc(g, j, xp, P) + ((1.0 + mm) * ri) * ld(xp + (size_t)j * P)) +
+                     (d1_rowc(g, j, xm, P) + ((1.0 - mm) * ri) * ld(xm + (size_t)j * P))) +
+              kap * ci(ld(xz + (size_t)j * P));
+  }
+  const int op = m * kp1 + ka;
+  const size_t ns = I.nops;
+  const double a00 = I.ainv[op], a01 = I.ainv[ns + op], a10 = I.ainv[2 * ns + op], a11 = I.ainv[3 * ns + op];
+  const Cd l1 = {-(a00 * beta[0].x + a01 * beta[1].x), -(a00 * beta[0].y + a01 * beta[1].y)};
+  const Cd l2 = {-(a10 * beta[0].x + a11 * beta[1].x), -(a10 * beta[0].y + a11 * beta[1].y)};
+  st(lam + 2 * (size_t)md, l1);
+  st(lam + 2 * (size_t)md + 1, l2);
+}
+
+struct Vals {
+  Cd ur, ut, uz, T, p;
+};
+
+__device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
+                                            const double2 *__restrict__ sx,
+                                            const double2 *__restrict__ sp,
+                                            const double2 *__restrict__ lam, int j, int md) {
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  Cd xp = ld(sx + (size_t)j * P + md);
+  Cd xm = ld(sx + ((size_t)n + j) * P + md);
+  Cd xz = ld(sx + ((size_t)2 * n + j) * P + md);
+  Cd p = ld(sp + (size_t)j * P + md);
+  Vals v;
+  if (!(m == 0 && ka == 0)) {
+    const double kap = (double)(kk - d.kmax) * d.kz;
+    const Cd l1 = ld(lam + 2 * (size_t)md), l2 = ld(lam + 2 * (size_t)md + 1);
+    const size_t ns = I.nops;
+    const int op = m * kp1 + ka;
+    auto Rv = [&](int s) { return I.resp[((size_t)s * n + j) * ns + op]; };
+    p = p + Rv(0) * l1 + Rv(1) * l2;
+    xp = xp + Rv(2) * l1 + Rv(3) * l2;
+    xm = xm + Rv(4) * l1 + Rv(5) * l2;
+    // X_z,j = -i kappa h_j
+    const Cd hz = Rv(6) * l1 + Rv(7) * l2;
+    xz = xz - kap * ci(hz);
+  }
+  v.ur = 0.5 * (xp + xm);
+  const Cd dd = xp - xm;  // u_theta = (X+ - X-) / (2 i)
+  v.ut = {0.5 * dd.y, -0.5 * dd.x};
+  v.uz = xz;
+  v.T = d.heated ? ld(sx + ((size_t)3 * n + j) * P + md) : Cd{0, 0};
+  v.p = p;
+  return v;
+}
+
+__global__ void k_finalize(Dims d, Influence I, const double2 *__restrict__ sx,
+                           const double2 *__restrict__ sp, const double2 *__restrict__ lam,
+                           double2 *__restrict__ out, double2 *__restrict__ pout) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  Vals v = final_value(d, I, sx, sp, lam, j, md);
+  if (md < d.mz) {  // m = 0: Hermitian projection
+    Vals w = final_value(d, I, sx, sp, lam, j, d.mz - 1 - md);
+    auto h = [](Cd a, Cd b) { return Cd{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)}; };
+    v.ur = h(v.ur, w.ur);
+    v.ut = h(v.ut, w.ut);
+    v.uz = h(v.uz, w.uz);
+    v.T = h(v.T, w.T);
+    v.p = h(v.p, w.p);
+  }
+  st(out + ((size_t)0 * n + j) * P + md, v.ur);
+  st(out + ((size_t)1 * n + j) * P + md, v.ut);
+  st(out + ((size_t)2 * n + j) * P + md, v.uz);
+  if (d.heated) st(out + ((size_t)3 * n + j) * P + md, v.T);
+  if (pout) st(pout + (size_t)j * P + md, v.p);
+}
+
+// Perturbation energy partial sums: w_j r_j c_m |u - U_b|^2 per block.
+__global__ void k_energy_part(Dims d, Grid g, const double2 *__restrict__ u, double *__restrict__ part) {
+  __shared__ double red[16];
+  const size_t P = d.nmodes;
+  const size_t total = (size_t)d.nr * P;
+  double acc = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / P);
+    const int md = (int)(idx - (size_t)j * P);
+    const int m = md / d.mz;
+    double s = 0.0;
+    for (int f = 0; f < 3; ++f) {
+      double2 v = u[((size_t)f * d.nr + j) * P + md];
+      if (f == 1 && md == d.kmax) v.x -= d.a_cou * g.r[j] + d.b_cou * g.rinv[j];
+      s += v.x * v.x + v.y * v.y;
+    }
+    acc += (m == 0 ? 1.0 : 2.0) * g.ccw[j] * g.r[j] * s;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+    part[blockIdx.x] = r;
+  }
+}
+
+__global__ void k_energy_final(const double *__restrict__ part, int n, double scale, double *out) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+    out[0] = r * scale;
+  }
+}
+
+// u~ = herm(amps) * g(r), g = 16 (r - r_i)^2 (r_o - r)^2.
+__global__ void k_seed(Dims d, Grid g, const double2 *__restrict__ amps, double2 *__restrict__ out) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int f = blockIdx.z;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  Cd a = ld(amps + (size_t)f * P + md);
+  if (md < d.mz) {
+    const Cd b = ld(amps + (size_t)f * P + (d.mz - 1 - md));
+    a = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+  }
+  if (md == d.kmax) a = {0, 0};
+  const double r = g.r[j];
+  const double s = 16.0 * (r - d.r_i) * (r - d.r_i) * (d.r_o - r) * (d.r_o - r);
+  st(out + ((size_t)f * d.nr + j) * P + md, s * a);
+}
+
+// out += basic state; T: out_T = T_c delta_00 + u~_T (unprojected).
+__global__ void k_add_base(Dims d, Grid g, const double2 *__restrict__ pert, double2 *__restrict__ out) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const double r = g.r[j];
+  if (md == d.kmax) {
+    double2 *p = out + ((size_t)1 * d.nr + j) * P + md;
+    p->x += d.a_cou * r + d.b_cou * g.rinv[j];
+  }
+  if (d.heated) {
+    Cd t = ld(pert + ((size_t)3 * d.nr + j) * P + md);
+    if (md == d.kmax) t.x += 0.5 + log(r / d.r_i) / log(d.r_i / d.r_o);
+    st(out + ((size_t)3 * d.nr + j) * P + md, t);
+  }
+}
+
+inline dim3 mode_grid(const nsc_ctx *c, int y, int z = 1) {
+  return dim3((c->d.nmodes + 255) / 256, y, z);
+}
+
+}  // namespace
+
+hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha, double beta) {
+  hipLaunchKernelGGL(k_factor, dim3((f->nops + kFacThreads - 1) / kFacThreads), dim3(kFacThreads), 0,
+                     c->stream, c->d, c->g, *f, kind, alpha, beta, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_setup(const nsc_ctx *c) {
+  hipLaunchKernelGGL(k_influence_setup, dim3((c->inf.nops + 63) / 64), dim3(64), 0, c->stream,
+                     c->d, c->g, c->fp, c->fv, c->inf);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const double *nq,
+                      double dt, double cc) {
+  hipLaunchKernelGGL(k_rhs, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(u), reinterpret_cast<const double2 *>(nn),
+                     reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_f),
+                     1.0 / dt, cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_div(const nsc_ctx *c) {
+  hipLaunchKernelGGL(k_div, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<double2 *>(c->s_g));
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_pt(const nsc_ctx *c, const double *nn, const double *nq, double cc,
+                           int walls, int want_p) {
+  hipLaunchKernelGGL(k_solve_pt, mode_grid(c, c->d.heated ? 2 : 1), dim3(256), 0, c->stream, c->d,
+                     c->g, c->fp, c->fp00, c->ft, reinterpret_cast<const double2 *>(c->s_g),
+                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<const double2 *>(nn),
+                     reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_p),
+                     reinterpret_cast<double2 *>(c->s_x) + (size_t)3 * c->d.nr * c->d.nmodes, cc,
+                     walls, want_p);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_vel(const nsc_ctx *c, int walls) {
+  hipLaunchKernelGGL(k_solve_vel, mode_grid(c, 3), dim3(256), 0, c->stream, c->d, c->g, c->fv,
+                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<const double2 *>(c->s_p),
+                     reinterpret_cast<double2 *>(c->s_x), walls);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence(const nsc_ctx *c) {
+  hipLaunchKernelGGL(k_influence, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->g, c->inf,
+                     reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<double2 *>(c->s_lam));
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out) {
+  hipLaunchKernelGGL(k_finalize, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->inf,
+                     reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<const double2 *>(c->s_p),
+                     reinterpret_cast<const double2 *>(c->s_lam), reinterpret_cast<double2 *>(out),
+                     reinterpret_cast<double2 *>(p_out));
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const nsc_ctx *c, const double *u, double *e_dev) {
+  hipLaunchKernelGGL(k_energy_part, dim3(c->e_nblk), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(u), c->e_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, c->stream, c->e_part, c->e_nblk,
+                     M_PI * c->d.lz, e_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(const nsc_ctx *c, const double *amps, double *out_pert) {
+  hipLaunchKernelGGL(k_seed, mode_grid(c, c->d.nr, c->d.f), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(amps), reinterpret_cast<double2 *>(out_pert));
+  return hipGetLastError();
+}
+
+hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *out) {
+  hipLaunchKernelGGL(k_add_base, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(pert_tilde), reinterpret_cast<double2 *>(out));
+  return hipGetLastError();
+}
+
+}  // namespace nsc

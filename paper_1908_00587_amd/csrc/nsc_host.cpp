@@ -1,0 +1,554 @@
+// Host runtime of libnsc.so: argument validation, radial discretisation
+// tables, transform plans, device memory, and the orchestration of the
+// nonlinear term, the per-mode radial solves and the predictor--corrector
+// step (sections 2.1 and 2.2 of the nsCouette paper).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nsc_internal.h"
+
+using namespace nsc;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Argument checks (pure host code, no HIP call)
+// ---------------------------------------------------------------------------
+bool plan_fft(int n, FftPlan *p) {
+  if (n < 2 || n > kMaxFFT) return false;
+  int rem = n;
+  int nst = 0;
+  int r[kMaxStages];
+  while (rem % 5 == 0) { rem /= 5; r[nst++] = 5; }
+  while (rem % 3 == 0) { rem /= 3; r[nst++] = 3; }
+  int a = 0;
+  while (rem % 2 == 0) { rem /= 2; ++a; }
+  if (rem != 1) return false;
+  while (a >= 3 && a != 4) { r[nst++] = 8; a -= 3; }
+  while (a >= 2) { r[nst++] = 4; a -= 2; }
+  if (a == 1) r[nst++] = 2;
+  if (nst > kMaxStages) return false;
+  p->n = n;
+  p->nst = nst;
+  p->min_radix = 8;
+  for (int i = 0; i < nst; ++i) {
+    p->radix[i] = r[i];
+    if (r[i] < p->min_radix) p->min_radix = r[i];
+  }
+  return true;
+}
+
+int validate(double eta, double Re_i, double Re_o, double Ra, double Pr, int N_r, int M_theta,
+             int M_z, double L_z) {
+  if (!(eta > 0.0 && eta < 1.0)) return NSC_ERR_ARG;
+  if (!std::isfinite(Re_i) || !std::isfinite(Re_o) || !std::isfinite(Ra)) return NSC_ERR_ARG;
+  if (Ra < 0.0) return NSC_ERR_ARG;
+  if (Ra != 0.0 && !(Pr > 0.0 && std::isfinite(Pr))) return NSC_ERR_ARG;
+  if (N_r < kStencil || N_r > 4096) return NSC_ERR_ARG;
+  if (M_theta < 1 || M_z < 1 || (M_z % 2) == 0) return NSC_ERR_ARG;
+  if (!(L_z > 0.0 && std::isfinite(L_z))) return NSC_ERR_ARG;
+  FftPlan pt, pz;
+  if (!plan_fft(3 * M_theta, &pt)) return NSC_ERR_ARG;
+  if (!plan_fft(3 * ((M_z - 1) / 2 + 1), &pz)) return NSC_ERR_ARG;
+  return NSC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Radial discretisation (host, FP64)
+// ---------------------------------------------------------------------------
+// Weights of derivative orders 0..2 at z from the nodes x[0..n-1] by the
+// recursive construction of B. Fornberg (Math. Comp. 51, 1988): each new
+// node updates the interpolant's derivative weights of all earlier nodes.
+void fd_weights(double z, const double *x, int n, double *c /* [n][3] */) {
+  for (int i = 0; i < 3 * n; ++i) c[i] = 0.0;
+  double c1 = 1.0, c4 = x[0] - z;
+  c[0] = 1.0;
+  for (int i = 1; i < n; ++i) {
+    const int mn = i < 2 ? i : 2;
+    double c2 = 1.0;
+    const double c5 = c4;
+    c4 = x[i] - z;
+    for (int j = 0; j < i; ++j) {
+      const double c3 = x[i] - x[j];
+      c2 *= c3;
+      if (j == i - 1) {
+        for (int k = mn; k >= 1; --k)
+          c[i * 3 + k] = c1 * (k * c[(i - 1) * 3 + k - 1] - c5 * c[(i - 1) * 3 + k]) / c2;
+        c[i * 3] = -c1 * c5 * c[(i - 1) * 3] / c2;
+      }
+      for (int k = mn; k >= 1; --k) c[j * 3 + k] = (c4 * c[j * 3 + k] - k * c[j * 3 + k - 1]) / c3;
+      c[j * 3] = c4 * c[j * 3] / c3;
+    }
+    c1 = c2;
+  }
+}
+
+// Clenshaw--Curtis weights on x_j = cos(j pi / N), j = 0..N (closed form of
+// the interpolatory rule), symmetric so the order of the nodes is irrelevant.
+void cc_weights_host(int npts, double *w) {
+  const int N = npts - 1;
+  for (int j = 0; j <= N; ++j) {
+    const double cj = (j == 0 || j == N) ? 1.0 : 2.0;
+    long double s = 1.0L;
+    for (int k = 1; k <= N / 2; ++k) {
+      const long double bk = (2 * k == N) ? 1.0L : 2.0L;
+      s -= bk / (4.0L * k * k - 1.0L) * cosl(2.0L * k * j * 3.14159265358979323846264338327950288L / N);
+    }
+    w[j] = (double)(cj / N * s);
+  }
+}
+
+void twiddles(int n, double *t64, float *t32) {
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int t = 0; t < n; ++t) {
+    const long double a = 2.0L * pi * (long double)t / (long double)n;
+    const double c = (double)cosl(a), s = -(double)sinl(a);
+    t64[2 * t] = c;
+    t64[2 * t + 1] = s;
+    t32[2 * t] = (float)cosl(a);
+    t32[2 * t + 1] = -(float)sinl(a);
+  }
+}
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) return NSC_ERR_DEVICE;   \
+  } while (0)
+
+int dmalloc(void **p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return NSC_ERR_OOM;
+  if (e != hipSuccess) return NSC_ERR_DEVICE;
+  return NSC_OK;
+}
+
+#define TRY(x)                 \
+  do {                         \
+    int s_ = (x);              \
+    if (s_ != NSC_OK) return s_; \
+  } while (0)
+
+bool mul_ok(size_t a, size_t b, size_t *out) {
+  if (a != 0 && b > SIZE_MAX / a) return false;
+  *out = a * b;
+  return true;
+}
+
+int alloc_factors(Factors *f, int nq, int kp1, int nr) {
+  f->nq = nq;
+  f->nops = nq * kp1;
+  TRY(dmalloc((void **)&f->vals, (size_t)nr * kSlots * f->nops * sizeof(double)));
+  TRY(dmalloc((void **)&f->edge, (size_t)kEdge * f->nops * sizeof(double)));
+  return NSC_OK;
+}
+
+void free_factors(Factors *f) {
+  if (f->vals) (void)hipFree(f->vals);
+  if (f->edge) (void)hipFree(f->edge);
+  f->vals = f->edge = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Stage timing (optional, synchronising)
+// ---------------------------------------------------------------------------
+struct StageTimer {
+  nsc_ctx *c;
+  int stage;
+  StageTimer(nsc_ctx *ctx, int s) : c(ctx), stage(s) {
+    if (c->profiling) (void)hipEventRecord(c->ev0, c->stream);
+  }
+  ~StageTimer() {
+    if (c->profiling) {
+      (void)hipEventRecord(c->ev1, c->stream);
+      (void)hipEventSynchronize(c->ev1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+      c->stage_ms[stage] += ms;
+      c->stage_cnt[stage] += 1.0;
+    }
+  }
+};
+
+int ensure_factors(nsc_ctx *c, double dt, double cc) {
+  if (dt == c->fac_dt && cc == c->fac_c) return NSC_OK;
+  StageTimer t(c, 10);
+  HIPCHK(launch_factor(c, &c->fv, OP_HELMHOLTZ, 1.0 / dt, cc));
+  if (c->d.heated) HIPCHK(launch_factor(c, &c->ft, OP_HELMHOLTZ, 1.0 / dt, cc / c->d.pr));
+  HIPCHK(launch_influence_setup(c));
+  c->fac_dt = dt;
+  c->fac_c = cc;
+  return NSC_OK;
+}
+
+int nonlinear_impl(nsc_ctx *c, const double *u, double *nh, double *cfl_out) {
+  {
+    StageTimer t(c, 0);
+    HIPCHK(launch_zinv(c, c->precision, u));
+  }
+  {
+    StageTimer t(c, 1);
+    HIPCHK(launch_theta(c, c->precision, cfl_out != nullptr));
+  }
+  {
+    StageTimer t(c, 2);
+    HIPCHK(launch_zfwd(c, c->precision, u, nh));
+  }
+  if (cfl_out) {
+    StageTimer t(c, 3);
+    HIPCHK(launch_cfl_final(c, cfl_out));
+  }
+  return NSC_OK;
+}
+
+int solve_impl(nsc_ctx *c, const double *un, const double *nn, const double *nq, double *out,
+               double *pout, double dt, double cc, int walls) {
+  TRY(ensure_factors(c, dt, cc));
+  {
+    StageTimer t(c, 4);
+    HIPCHK(launch_rhs(c, un, nn, nq, dt, cc));
+  }
+  {
+    StageTimer t(c, 5);
+    HIPCHK(launch_div(c));
+  }
+  {
+    StageTimer t(c, 6);
+    HIPCHK(launch_solve_pt(c, nn, nq, cc, walls, pout != nullptr));
+  }
+  {
+    StageTimer t(c, 7);
+    HIPCHK(launch_solve_vel(c, walls));
+  }
+  {
+    StageTimer t(c, 8);
+    HIPCHK(launch_influence(c));
+  }
+  {
+    StageTimer t(c, 9);
+    HIPCHK(launch_finalize(c, out, pout));
+  }
+  return NSC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Public ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *nsc_strerror(int status) {
+  switch (status) {
+    case NSC_OK: return "ok";
+    case NSC_ERR_ARG: return "invalid argument";
+    case NSC_ERR_DEVICE: return "HIP device or runtime error";
+    case NSC_ERR_OOM: return "device allocation failed or size overflow";
+    case NSC_ERR_NONFINITE: return "non-finite value detected";
+    case NSC_ERR_DT: return "time step collapsed below 1e-12";
+    case NSC_ERR_STATE: return "call not valid in the current context state";
+    default: return "unknown status";
+  }
+}
+
+int nsc_destroy(nsc_ctx *c) {
+  if (!c) return NSC_OK;
+  void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
+                  c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
+                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->inf.resp, c->inf.ainv};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  free_factors(&c->fv);
+  free_factors(&c->ft);
+  free_factors(&c->fp);
+  free_factors(&c->fp00);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->ev_cfl) (void)hipEventDestroy(c->ev_cfl);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete[] c->h_r;
+  delete c;
+  return NSC_OK;
+}
+
+static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra, double Pr,
+                     int N_r, int M_theta, int M_z, double L_z) {
+  Dims &d = c->d;
+  d.nr = N_r;
+  d.mt = M_theta;
+  d.mz = M_z;
+  d.kmax = (M_z - 1) / 2;
+  d.nt = 3 * M_theta;
+  d.nz = 3 * (d.kmax + 1);
+  d.nmodes = M_theta * M_z;
+  d.heated = Ra != 0.0 ? 1 : 0;
+  d.f = d.heated ? 4 : 3;
+  d.kz = 2.0 * M_PI / L_z;
+  d.pr = d.heated ? Pr : 1.0;
+  d.gr = d.heated ? Ra / Pr : 0.0;
+  d.re_i = Re_i;
+  d.re_o = Re_o;
+  d.r_i = eta / (1.0 - eta);
+  d.r_o = 1.0 / (1.0 - eta);
+  d.lz = L_z;
+  d.a_cou = (Re_o * d.r_o - Re_i * d.r_i) / (d.r_o * d.r_o - d.r_i * d.r_i);
+  d.b_cou = d.r_i * (Re_i - d.a_cou * d.r_i);
+  c->eta = eta;
+  c->ra = Ra;
+  c->n_in = d.heated ? 9 : 6;
+  c->n_out = d.heated ? 4 : 3;
+  plan_fft(d.nt, &c->plan_t);
+  plan_fft(d.nz, &c->plan_z);
+
+  // size guards
+  size_t field, tmp;
+  if (!mul_ok((size_t)d.nr, (size_t)d.nmodes, &field) || !mul_ok(field, 16, &field))
+    return NSC_ERR_OOM;
+  size_t inter;
+  if (!mul_ok((size_t)d.nr * d.nz, (size_t)d.mt, &inter) || !mul_ok(inter, 16, &inter))
+    return NSC_ERR_OOM;
+  (void)tmp;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return NSC_ERR_DEVICE;
+  HIPCHK(hipGetDevice(&c->device));
+
+  // host tables
+  const int n = d.nr;
+  c->h_r = new (std::nothrow) double[n];
+  if (!c->h_r) return NSC_ERR_OOM;
+  std::vector<double> rinv(n), d1(n * kStencil), d2(n * kStencil), dr(n), ccw(n);
+  std::vector<int> s(n);
+  for (int j = 0; j < n; ++j) {
+    const double x = std::cos(M_PI * (double)(n - 1 - j) / (double)(n - 1));
+    c->h_r[j] = 0.5 * (d.r_i + d.r_o) + 0.5 * x;
+  }
+  for (int j = 0; j < n; ++j) {
+    rinv[j] = 1.0 / c->h_r[j];
+    int sj = j - kHalf;
+    if (sj < 0) sj = 0;
+    if (sj > n - kStencil) sj = n - kStencil;
+    s[j] = sj;
+    double w[kStencil * 3];
+    fd_weights(c->h_r[j], c->h_r + sj, kStencil, w);
+    for (int t = 0; t < kStencil; ++t) {
+      d1[j * kStencil + t] = w[t * 3 + 1];
+      d2[j * kStencil + t] = w[t * 3 + 2];
+    }
+    const double lo = j > 0 ? c->h_r[j] - c->h_r[j - 1] : c->h_r[1] - c->h_r[0];
+    const double hi = j < n - 1 ? c->h_r[j + 1] - c->h_r[j] : c->h_r[n - 1] - c->h_r[n - 2];
+    dr[j] = lo < hi ? lo : hi;
+  }
+  cc_weights_host(n, ccw.data());
+  for (int j = 0; j < n; ++j) ccw[j] *= 0.5;
+
+  // device tables: one allocation
+  const size_t nd = (size_t)n * (1 + 1 + kStencil * 2 + 1 + 1);
+  TRY(dmalloc(&c->tables, nd * sizeof(double) + (size_t)n * sizeof(int) + 256));
+  double *base = (double *)c->tables;
+  double *p_r = base, *p_rinv = p_r + n, *p_d1 = p_rinv + n, *p_d2 = p_d1 + n * kStencil,
+         *p_dr = p_d2 + n * kStencil, *p_cc = p_dr + n;
+  int *p_s = (int *)(p_cc + n);
+  HIPCHK(hipMemcpy(p_r, c->h_r, n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_rinv, rinv.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_d1, d1.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_d2, d2.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_dr, dr.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_cc, ccw.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_s, s.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc};
+
+  // twiddles
+  {
+    std::vector<double> t64(2 * d.nt);
+    std::vector<float> t32(2 * d.nt);
+    twiddles(d.nt, t64.data(), t32.data());
+    TRY(dmalloc((void **)&c->tw64_t, t64.size() * sizeof(double)));
+    TRY(dmalloc((void **)&c->tw32_t, t32.size() * sizeof(float)));
+    HIPCHK(hipMemcpy(c->tw64_t, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tw32_t, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    std::vector<double> z64(2 * d.nz);
+    std::vector<float> z32(2 * d.nz);
+    twiddles(d.nz, z64.data(), z32.data());
+    TRY(dmalloc((void **)&c->tw64_z, z64.size() * sizeof(double)));
+    TRY(dmalloc((void **)&c->tw32_z, z32.size() * sizeof(float)));
+    HIPCHK(hipMemcpy(c->tw64_z, z64.data(), z64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->tw32_z, z32.data(), z32.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+
+  // workspaces
+  TRY(dmalloc(&c->zbuf, inter * c->n_in));
+  TRY(dmalloc(&c->wbuf, inter * c->n_out));
+  c->cfl_nblk = d.nz * d.nr;
+  TRY(dmalloc((void **)&c->cfl_part, (size_t)c->cfl_nblk * sizeof(double)));
+  TRY(dmalloc((void **)&c->cfl_val, 4 * sizeof(double)));
+  c->e_nblk = 1024;
+  TRY(dmalloc((void **)&c->e_part, (size_t)c->e_nblk * sizeof(double)));
+  TRY(dmalloc((void **)&c->s_f, field * 4));
+  TRY(dmalloc((void **)&c->s_g, field));
+  TRY(dmalloc((void **)&c->s_p, field));
+  TRY(dmalloc((void **)&c->s_x, field * 4));
+  TRY(dmalloc((void **)&c->s_lam, (size_t)d.nmodes * 32));
+  TRY(dmalloc((void **)&c->s_u1, field * d.f));
+  TRY(dmalloc((void **)&c->s_nn, field * d.f));
+  TRY(dmalloc((void **)&c->s_nq, field * d.f));
+  TRY(dmalloc((void **)&c->s_tmp, field * d.f));
+  HIPCHK(hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_cfl, hipEventDisableTiming));
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+
+  // factors
+  const int kp1 = d.kmax + 1;
+  TRY(alloc_factors(&c->fv, d.mt + 1, kp1, n));
+  TRY(alloc_factors(&c->fp, d.mt, kp1, n));
+  if (d.heated) TRY(alloc_factors(&c->ft, d.mt, kp1, n));
+  c->fp00.nq = 1;
+  c->fp00.nops = 1;
+  TRY(dmalloc((void **)&c->fp00.vals, (size_t)n * kSlots * sizeof(double)));
+  TRY(dmalloc((void **)&c->fp00.edge, (size_t)kEdge * sizeof(double)));
+  c->inf.nops = d.mt * kp1;
+  TRY(dmalloc((void **)&c->inf.resp, (size_t)8 * n * c->inf.nops * sizeof(double)));
+  TRY(dmalloc((void **)&c->inf.ainv, (size_t)4 * c->inf.nops * sizeof(double)));
+
+  // Delta t-independent pressure factors
+  HIPCHK(launch_factor(c, &c->fp, OP_POISSON, 0.0, 0.0));
+  HIPCHK(launch_factor(c, &c->fp00, OP_MEAN_PRESSURE, 0.0, 0.0));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return NSC_OK;
+}
+
+int nsc_init(double eta, double Re_i, double Re_o, double Ra, double Pr, int N_r, int M_theta,
+             int M_z, double L_z, nsc_ctx **out) {
+  if (!out) return NSC_ERR_ARG;
+  *out = nullptr;
+  int st = validate(eta, Re_i, Re_o, Ra, Pr, N_r, M_theta, M_z, L_z);
+  if (st != NSC_OK) return st;
+  nsc_ctx *c = new (std::nothrow) nsc_ctx();
+  if (!c) return NSC_ERR_OOM;
+  st = init_impl(c, eta, Re_i, Re_o, Ra, Pr, N_r, M_theta, M_z, L_z);
+  if (st != NSC_OK) {
+    nsc_destroy(c);
+    return st;
+  }
+  *out = c;
+  return NSC_OK;
+}
+
+int nsc_set_stream(nsc_ctx *c, void *s) {
+  if (!c) return NSC_ERR_ARG;
+  c->stream = (hipStream_t)s;
+  return NSC_OK;
+}
+
+int nsc_set_precision(nsc_ctx *c, int mode) {
+  if (!c || (mode != NSC_FP64 && mode != NSC_MIXED)) return NSC_ERR_ARG;
+  c->precision = mode;
+  return NSC_OK;
+}
+
+int nsc_set_timestep(nsc_ctx *c, double dt, int dynamic, double cfl, double dt_max, int n_corr,
+                     double c_implicit) {
+  if (!c) return NSC_ERR_ARG;
+  if (!(dt > 0.0 && std::isfinite(dt)) || !(cfl > 0.0) || !(dt_max > 0.0) || n_corr < 0 ||
+      n_corr > 64 || !(c_implicit > 0.0 && c_implicit <= 1.0) || (dynamic != 0 && dynamic != 1))
+    return NSC_ERR_ARG;
+  c->dt = dt;
+  c->dynamic = dynamic;
+  c->cfl = cfl;
+  c->dt_max = dt_max;
+  c->n_corr = n_corr;
+  c->c = c_implicit;
+  return NSC_OK;
+}
+
+int nsc_nonlinear(nsc_ctx *c, const double *u, double *nh, double *cfl_dt_dev) {
+  if (!c || !u || !nh || (const void *)u == (const void *)nh) return NSC_ERR_ARG;
+  return nonlinear_impl(c, u, nh, cfl_dt_dev);
+}
+
+int nsc_radial_solve(nsc_ctx *c, const double *un, const double *nn, const double *nq, double *out,
+                     double *pout) {
+  if (!c || !un || !nn || !nq || !out) return NSC_ERR_ARG;
+  if ((const void *)out == (const void *)un || (const void *)out == (const void *)nn ||
+      (const void *)out == (const void *)nq)
+    return NSC_ERR_ARG;
+  return solve_impl(c, un, nn, nq, out, pout, c->dt, c->c, 1);
+}
+
+int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
+  if (!c || !u || !dt_inout) return NSC_ERR_ARG;
+  const double dt = *dt_inout;
+  if (!(dt > 0.0 && std::isfinite(dt))) return NSC_ERR_ARG;
+  const bool dyn = c->dynamic != 0;
+  TRY(nonlinear_impl(c, u, c->s_nn, dyn ? c->cfl_val : nullptr));
+  if (dyn) {
+    HIPCHK(hipMemcpyAsync(c->h_pinned, c->cfl_val, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
+  }
+  // predictor, then correctors; the last stage writes u in place (the
+  // finalising kernel reads only library scratch, never u^n)
+  TRY(solve_impl(c, u, c->s_nn, c->s_nn, c->n_corr == 0 ? u : c->s_u1, nullptr, dt, c->c, 1));
+  for (int q = 1; q <= c->n_corr; ++q) {
+    TRY(nonlinear_impl(c, c->s_u1, c->s_nq, nullptr));
+    TRY(solve_impl(c, u, c->s_nn, c->s_nq, q == c->n_corr ? u : c->s_u1, nullptr, dt, c->c, 1));
+  }
+  if (dyn) {
+    HIPCHK(hipEventSynchronize(c->ev_cfl));
+    const double dtc = c->h_pinned[0];
+    if (std::isnan(dtc)) return NSC_ERR_NONFINITE;
+    double cand = c->cfl * dtc;
+    if (cand > c->dt_max) cand = c->dt_max;
+    double next = dt;
+    if (cand < dt || cand > 1.1 * dt) next = cand;
+    if (!(next >= 1e-12)) return NSC_ERR_DT;
+    *dt_inout = next;
+  }
+  return NSC_OK;
+}
+
+int nsc_energy(nsc_ctx *c, const double *u, double *e_dev) {
+  if (!c || !u || !e_dev) return NSC_ERR_ARG;
+  HIPCHK(launch_energy(c, u, e_dev));
+  return NSC_OK;
+}
+
+int nsc_initial_state(nsc_ctx *c, const double *amps, double *out) {
+  if (!c || !amps || !out) return NSC_ERR_ARG;
+  HIPCHK(launch_seed(c, amps, c->s_tmp));
+  TRY(solve_impl(c, c->s_tmp, nullptr, nullptr, out, nullptr, 1e-3, 1.0, 0));
+  HIPCHK(launch_add_base(c, c->s_tmp, out));
+  return NSC_OK;
+}
+
+int nsc_get_grid(nsc_ctx *c, double *r, int n) {
+  if (!c || !r || n < c->d.nr) return NSC_ERR_ARG;
+  std::memcpy(r, c->h_r, sizeof(double) * c->d.nr);
+  return NSC_OK;
+}
+
+int nsc_set_profiling(nsc_ctx *c, int on) {
+  if (!c) return NSC_ERR_ARG;
+  c->profiling = on ? 1 : 0;
+  return NSC_OK;
+}
+
+int nsc_get_timings(nsc_ctx *c, double *ms, int n) {
+  if (!c || !ms || n < 0) return NSC_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (i < kNumStages) ms[i] = c->stage_ms[i];
+    else if (i < 2 * kNumStages) ms[i] = c->stage_cnt[i - kNumStages];
+    else ms[i] = 0.0;
+  }
+  for (int i = 0; i < kNumStages; ++i) c->stage_ms[i] = c->stage_cnt[i] = 0.0;
+  return NSC_OK;
+}
+
+}  // extern "C"

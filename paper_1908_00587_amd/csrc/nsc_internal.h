@@ -1,0 +1,141 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libnsc.so.  Not part of the public ABI (include/nsc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/nsc.h"
+
+namespace nsc {
+
+constexpr int kStencil = 9;    // nine-point radial stencils (section 2.1 default)
+constexpr int kHalf = 4;       // stencil half width
+constexpr int kSlots = 9;      // compact LU row: L[4] | 1/U_jj | U[4]
+constexpr int kEdge = 20;      // extra U entries of rows 0..3 + extra L of rows N-4..N-1
+constexpr int kMaxRadix = 8;
+constexpr int kMaxStages = 12;
+constexpr int kMaxFFT = 4096;
+constexpr int kFftThreads = 512;  // launch bound of the FFT kernels
+constexpr int kNumStages = 11;  // timed kernels (see nsc_get_timings)
+
+struct FftPlan {
+  int n = 0;
+  int nst = 0;
+  int min_radix = 8;
+  int radix[kMaxStages] = {0};
+};
+
+// Device-side read-only tables of the radial discretisation.
+struct Grid {
+  const double *r;     // [N_r] radial points
+  const double *rinv;  // [N_r] 1/r
+  const double *d1;    // [N_r][9] first-derivative weights
+  const double *d2;    // [N_r][9] second-derivative weights
+  const int *s;        // [N_r] first node of each row's window
+  const double *dr;    // [N_r] local spacing for the CFL bound
+  const double *ccw;   // [N_r] Clenshaw--Curtis weights on [r_i, r_o]
+};
+
+// Problem sizes and physical constants passed by value to kernels.
+struct Dims {
+  int nr, mt, mz, kmax, nt, nz, nmodes, f, heated;
+  double kz, gr, pr, re_i, re_o, a_cou, b_cou, r_i, r_o, lz;
+};
+
+// Compact no-pivot LU factors of a family of radial operators.
+// vals: [N_r][kSlots][nops], edge: [kEdge][nops]; op = q * (K+1) + |k|.
+struct Factors {
+  double *vals = nullptr;
+  double *edge = nullptr;
+  int nq = 0;   // number of q values
+  int nops = 0;
+};
+
+// Homogeneous (influence) responses per (m, |k|), op = m*(K+1)+|k|:
+// resp: [8][N_r][nops] = p1, p2, X+1, X+2, X-1, X-2, h1, h2 (X_z,j = -i kappa h_j)
+// ainv: [4][nops] the inverse 2x2 influence matrix.
+struct Influence {
+  double *resp = nullptr;
+  double *ainv = nullptr;
+  int nops = 0;
+};
+
+}  // namespace nsc
+
+struct nsc_ctx {
+  nsc::Dims d{};
+  double eta = 0, ra = 0;
+  int n_in = 0, n_out = 0;
+  // time integration
+  double dt = 1e-3, cfl = 0.5, dt_max = 1e-3, c = 0.5;
+  int dynamic = 0, n_corr = 1, precision = NSC_FP64;
+  // cached factor parameters
+  double fac_dt = -1.0, fac_c = -1.0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // host copies
+  double *h_r = nullptr;
+  // device tables
+  nsc::Grid g{};
+  void *tables = nullptr;  // single allocation backing g
+  double *tw64_t = nullptr, *tw64_z = nullptr;  // [n][2] twiddles e^{-2 pi i t/n}
+  float *tw32_t = nullptr, *tw32_z = nullptr;
+  nsc::FftPlan plan_t{}, plan_z{};
+  // factors
+  nsc::Factors fv{}, ft{}, fp{}, fp00{};
+  nsc::Influence inf{};
+  // workspaces
+  void *zbuf = nullptr;    // [n_in][N_r][N_z][M_theta] complex (FP64 size)
+  void *wbuf = nullptr;    // [n_out][N_r][N_z][M_theta] complex
+  double *cfl_part = nullptr;  // per-block CFL partial minima
+  int cfl_nblk = 0;
+  double *cfl_val = nullptr;   // [2] scalars
+  double *e_part = nullptr;    // energy partials
+  int e_nblk = 0;
+  double *s_f = nullptr;    // [4][N_r][modes] complex right sides
+  double *s_g = nullptr;    // [N_r][modes] complex divergence
+  double *s_p = nullptr;    // [N_r][modes] complex p0
+  double *s_x = nullptr;    // [4][N_r][modes] complex X0+, X0-, X0z, T
+  double *s_lam = nullptr;  // [modes][2] complex
+  double *s_u1 = nullptr;   // [F][N_r][modes] complex intermediate state
+  double *s_nn = nullptr;   // [F][N_r][modes] complex N^n
+  double *s_nq = nullptr;   // [F][N_r][modes] complex N^q
+  double *s_tmp = nullptr;  // [F][N_r][modes] complex scratch
+  double *h_pinned = nullptr;  // pinned host scalar(s)
+  hipEvent_t ev_cfl = nullptr;
+  // profiling
+  int profiling = 0;
+  double stage_ms[nsc::kNumStages] = {0};
+  double stage_cnt[nsc::kNumStages] = {0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace nsc {
+
+// ---- launchers (kernels in *.hip) -----------------------------------------
+hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u);
+hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl);
+hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat);
+hipError_t launch_cfl_final(const nsc_ctx *c, double *out);
+
+hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha,
+                         double beta);
+hipError_t launch_influence_setup(const nsc_ctx *c);
+hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn,
+                      const double *nq, double dt, double cc);
+hipError_t launch_div(const nsc_ctx *c);
+hipError_t launch_solve_pt(const nsc_ctx *c, const double *nn, const double *nq,
+                           double cc, int walls, int want_p);
+hipError_t launch_solve_vel(const nsc_ctx *c, int walls);
+hipError_t launch_influence(const nsc_ctx *c);
+hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out);
+hipError_t launch_energy(const nsc_ctx *c, const double *u, double *e_dev);
+hipError_t launch_seed(const nsc_ctx *c, const double *amps, double *out_pert);
+hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *out);
+
+// operator kinds for launch_factor
+enum { OP_HELMHOLTZ = 0, OP_POISSON = 1, OP_MEAN_PRESSURE = 2 };
+
+}  // namespace nsc
