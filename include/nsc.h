@@ -145,6 +145,30 @@ int nsc_energy(nsc_ctx *ctx, const double *u_hat, double *e_dev);
  * Leaves the time-step settings unchanged.  u_hat_out: [F][N_r][M_theta][M_z]. */
 int nsc_initial_state(nsc_ctx *ctx, const double *amps_dev, double *u_hat_out);
 
+/* ---- Discrete adjoint (vector--Jacobian products, FP64 inner product
+ * <a, b> = sum over every stored entry of Re(conj(a) b); the gradient of a
+ * real function w.r.t. a complex entry is dF/dRe + i dF/dIm).  Used for
+ * gradients of flow functionals with respect to initial perturbations
+ * (optimal-perturbation search) by checkpoint-and-recompute over steps. */
+
+/* u_bar += (dN/du at u_hat)^T n_bar for the nonlinear term of nsc_nonlinear
+ * (same precision policy).  u_hat, n_bar, u_bar: [F][N_r][M_theta][M_z];
+ * u_bar must not alias the inputs.  Uses the context workspaces. */
+int nsc_nonlinear_vjp(nsc_ctx *ctx, const double *u_hat, const double *n_bar,
+                      double *u_bar);
+
+/* Transpose of the implicit stage of nsc_radial_solve (same step size and
+ * implicit weight; wall data are constants and drop out): with u_bar_out the
+ * adjoint of the stage output, accumulates u_bar_n += dS/du_n^T u_bar_out,
+ * n_bar_n += dS/dN^n^T u_bar_out, n_bar_q += dS/dN^q^T u_bar_out.  All
+ * [F][N_r][M_theta][M_z], pairwise distinct. */
+int nsc_radial_solve_vjp(nsc_ctx *ctx, const double *u_bar_out,
+                         double *u_bar_n, double *n_bar_n, double *n_bar_q);
+
+/* Gradient of nsc_energy: g = 2 pi L_z w_j r_j c_m (u - U_b) for the
+ * velocity fields, 0 for T (c_0 = 1, c_m = 2).  g is written, not added. */
+int nsc_energy_grad(nsc_ctx *ctx, const double *u_hat, double *g);
+
 /* Radial grid points r_j (HOST array of n >= N_r doubles). */
 int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
 

@@ -281,7 +281,7 @@ def nonlinear_planes(p, u, rows, D1=None, r=None):
         torch.where(ur.abs() > 0, dr / ur.abs(), inf),
         torch.where(ut.abs() > 0, rr * dth / ut.abs(), inf),
         torch.where(uz.abs() > 0, dz / uz.abs(), inf)])
-    return Nhat, float(cand.min())
+    return Nhat, float(cand.detach().min())
 
 
 def nonlinear(p, u, D1=None, r=None):

@@ -42,6 +42,9 @@ def _bind(L):
         "nsc_step": ([P, P, ctypes.POINTER(D)], I),
         "nsc_energy": ([P, P, P], I),
         "nsc_initial_state": ([P, P, P], I),
+        "nsc_nonlinear_vjp": ([P, P, P, P], I),
+        "nsc_radial_solve_vjp": ([P, P, P, P, P], I),
+        "nsc_energy_grad": ([P, P, P], I),
         "nsc_get_grid": ([P, ctypes.POINTER(D), I], I),
         "nsc_get_timings": ([P, ctypes.POINTER(D), I], I),
         "nsc_set_profiling": ([P, I], I),

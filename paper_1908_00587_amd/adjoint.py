@@ -1,0 +1,122 @@
+"""Discrete adjoint of the time stepper: gradients of the perturbation
+kinetic energy after S steps with respect to the initial state
+(optimal-perturbation search), by checkpoint-and-recompute over steps.
+
+Every vector--Jacobian product runs in the library (nsc_nonlinear_vjp,
+nsc_radial_solve_vjp, nsc_energy_grad); this module only sequences them.
+The time-step schedule and the number of corrector stages are held fixed
+(not differentiated).  Inner product: sum over all stored entries of
+Re(conj(a) b), so a complex gradient entry is dE/dRe + i dE/dIm.
+"""
+import ctypes
+
+import torch
+
+from ._lib import check
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def nonlinear_vjp(ctx, u, nbar, ubar=None):
+    """ubar += (dN/du)^T nbar; returns ubar."""
+    if ubar is None:
+        ubar = torch.zeros_like(u)
+    ctx._sync_stream()
+    check(ctx._L.nsc_nonlinear_vjp(ctx._h, _p(u), _p(nbar), _p(ubar)), "nsc_nonlinear_vjp")
+    return ubar
+
+
+def radial_solve_vjp(ctx, ubar_out, ubar_n=None, nbar_n=None, nbar_q=None):
+    """Accumulates the transposed implicit stage; returns (ubar_n, nbar_n, nbar_q)."""
+    ubar_n = torch.zeros_like(ubar_out) if ubar_n is None else ubar_n
+    nbar_n = torch.zeros_like(ubar_out) if nbar_n is None else nbar_n
+    nbar_q = torch.zeros_like(ubar_out) if nbar_q is None else nbar_q
+    ctx._sync_stream()
+    check(ctx._L.nsc_radial_solve_vjp(ctx._h, _p(ubar_out), _p(ubar_n), _p(nbar_n), _p(nbar_q)),
+          "nsc_radial_solve_vjp")
+    return ubar_n, nbar_n, nbar_q
+
+
+def energy_grad(ctx, u):
+    g = torch.empty_like(u)
+    ctx._sync_stream()
+    check(ctx._L.nsc_energy_grad(ctx._h, _p(u), _p(g)), "nsc_energy_grad")
+    return g
+
+
+def step_vjp(ctx, u, ubar_next, n_corr=1):
+    """Adjoint of one predictor--corrector step at state u (current dt):
+    recomputes the stage states, then walks the stages backwards."""
+    a = ctx.nonlinear(u)
+    stages = [ctx.radial_solve(u, a, a)]
+    for _ in range(n_corr):
+        stages.append(ctx.radial_solve(u, a, ctx.nonlinear(stages[-1])))
+    ubar = torch.zeros_like(u)
+    abar = torch.zeros_like(u)
+    xbar = ubar_next
+    for q in range(n_corr, 0, -1):
+        # X^(q+1) = S(u, a, N(X^(q)))
+        bbar = torch.zeros_like(u)
+        radial_solve_vjp(ctx, xbar, ubar, abar, bbar)
+        xbar = nonlinear_vjp(ctx, stages[q - 1], bbar)
+    # X^(1) = S(u, a, a)
+    bbar = torch.zeros_like(u)
+    radial_solve_vjp(ctx, xbar, ubar, abar, bbar)
+    abar += bbar
+    nonlinear_vjp(ctx, u, abar, ubar)
+    return ubar
+
+
+def rollout(ctx, u0, steps, dt):
+    """Forward: `steps` steps of size dt from a copy of u0."""
+    u = u0.clone()
+    for _ in range(steps):
+        ctx.step(u, dt)
+    return u
+
+
+class RolloutEnergy(torch.autograd.Function):
+    """E(u^S), u^{n+1} = Step(u^n), fixed dt; backward by checkpointing every
+    `ckpt_every` steps and recomputing each segment."""
+
+    @staticmethod
+    def forward(fctx, u0, ctx, steps, dt, ckpt_every, n_corr):
+        ctx.set_timestep(dt=dt, n_corr=n_corr)
+        ckpts = []
+        u = u0.detach().clone()
+        for n in range(steps):
+            if n % ckpt_every == 0:
+                ckpts.append(u.clone())
+            ctx.step(u, dt)
+        e = ctx.energy(u)
+        fctx.ctx = ctx
+        fctx.steps, fctx.dt, fctx.ckpt_every, fctx.n_corr = steps, dt, ckpt_every, n_corr
+        fctx.ckpts = ckpts
+        fctx.save_for_backward(u)
+        return e
+
+    @staticmethod
+    def backward(fctx, ge):
+        (uS,) = fctx.saved_tensors
+        ctx = fctx.ctx
+        ctx.set_timestep(dt=fctx.dt, n_corr=fctx.n_corr)
+        ubar = energy_grad(ctx, uS) * ge.to(uS.dtype)
+        steps, C = fctx.steps, fctx.ckpt_every
+        for s in range(len(fctx.ckpts) - 1, -1, -1):
+            n0 = s * C
+            n1 = min(steps, n0 + C)
+            states = [fctx.ckpts[s].clone()]
+            for _ in range(n0, n1 - 1):
+                x = states[-1].clone()
+                ctx.step(x, fctx.dt)
+                states.append(x)
+            for k in range(n1 - n0 - 1, -1, -1):
+                ubar = step_vjp(ctx, states[k], ubar, fctx.n_corr)
+        return ubar, None, None, None, None, None
+
+
+def rollout_energy(ctx, u0, steps, dt, ckpt_every=20, n_corr=1):
+    """Perturbation kinetic energy after `steps` steps; differentiable in u0."""
+    return RolloutEnergy.apply(u0, ctx, steps, dt, ckpt_every, n_corr)

@@ -286,6 +286,228 @@ __global__ void k_cfl_final(const double *__restrict__ part, int n, double *out)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector--Jacobian product of the nonlinear term.  With the inverse transform
+// Inv(x)_ab = Re sum c_m x_mk e^{i phi} and the forward F(f) = (N_theta N_z)^-1
+// sum f e^{-i phi}, the transposes are F^T g = Inv(g / c_m) / (N_theta N_z)
+// and Inv^T f = c_m * (unnormalised forward DFT of f).  For N = u x omega:
+// ubar = omega x Nbar, omegabar = Nbar x u; for N_T = -u . G: ubar -= Nbar_T G,
+// Gbar = -Nbar_T u.  Buoyancy: Tbar += Gr Nbar_z.
+// ---------------------------------------------------------------------------
+
+// Nbar (Hermitian-projected, divided by c_m and N_theta N_z) -> inverse z FFT.
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads)
+k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict__ W,
+           const C2<T> *__restrict__ tw, int tm, double scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  const int nz = d.nz, K = d.kmax, mz = d.mz;
+  const int ls = nz + 1;
+  const int mt0 = blockIdx.x * tm;
+  const int j = blockIdx.y;
+  const int f = blockIdx.z;
+  const int nl = min(tm, d.mt - mt0);
+  const size_t plane = (size_t)d.nmodes;
+  const double2 *src = nb + ((size_t)f * d.nr + j) * plane;
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int li = idx / nz;
+    const int b = idx - li * nz;
+    C2<T> val = {T(0), T(0)};
+    int k = INT_MIN;
+    if (b <= K) k = b;
+    else if (b >= nz - K) k = b - nz;
+    if (k != INT_MIN) {
+      const int m = mt0 + li;
+      const int kk = k + K;
+      double2 v = src[(size_t)m * mz + kk];
+      if (m == 0) {
+        const double2 w = src[mz - 1 - kk];
+        v = make_double2(0.5 * (v.x + w.x), 0.5 * (v.y - w.y));
+      }
+      const double s = (m == 0 ? 1.0 : 0.5) * scale;
+      val = {T(v.x * s), T(v.y * s)};
+    }
+    buf[li * ls + b] = val;
+  }
+  __syncthreads();
+  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tw);
+  C2<T> *out = W + ((size_t)f * d.nr + j) * nz * d.mt;
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int b = idx / nl;
+    const int li = idx - b * nl;
+    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + b];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pack_line(C2<T> *L, const C2<T> *zl, size_t fstride, int f1, int f2,
+                                          int nf, int nt, int mt) {
+  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
+    C2<T> v = {T(0), T(0)};
+    if (a == 0) {
+      C2<T> F1 = zl[f1 * fstride];
+      C2<T> F2 = f2 < nf ? zl[f2 * fstride] : C2<T>{T(0), T(0)};
+      v = {F1.x, F2.x};
+    } else if (a < mt) {
+      C2<T> F1 = zl[f1 * fstride + a];
+      C2<T> F2 = f2 < nf ? zl[f2 * fstride + a] : C2<T>{T(0), T(0)};
+      v = {F1.x - F2.y, F1.y + F2.x};
+    } else if (a > nt - mt) {
+      const int m = nt - a;
+      C2<T> F1 = zl[f1 * fstride + m];
+      C2<T> F2 = f2 < nf ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
+      v = {F1.x + F2.y, F2.x - F1.y};
+    }
+    L[a] = v;
+  }
+}
+
+// Per (r, z) line: forward fields from Z, adjoint outputs from W; pointwise
+// adjoint products; forward theta FFT of the input adjoints back into Z.
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads)
+k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
+            const C2<T> *__restrict__ tw, int n_in, int n_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  const int nt = d.nt, mt = d.mt;
+  const int ls = nt + 1;
+  const int b = blockIdx.x;
+  const int j = blockIdx.y;
+  const int npi = (n_in + 1) / 2;
+  const size_t fstride = (size_t)d.nr * d.nz * mt;
+  C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
+  const C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
+  for (int p = 0; p < npi; ++p) pack_line(buf + p * ls, zl, fstride, 2 * p, 2 * p + 1, n_in, nt, mt);
+  for (int p = 0; p < 2; ++p) pack_line(buf + (npi + p) * ls, wl, fstride, 2 * p, 2 * p + 1, n_out, nt, mt);
+  __syncthreads();
+  fft_lines<T, true, kMaxB>(buf, npi + 2, ls, pt, tw);
+  const bool heated = n_in > 6;
+  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
+    const C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
+    const C2<T> n0 = buf[npi * ls + a], n1 = buf[(npi + 1) * ls + a];
+    const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
+    const T nr_ = n0.x, nth = n0.y, nzz = n1.x, ntt = n1.y;
+    T bur = wt * nzz - wz * nth;
+    T but = wz * nr_ - wr * nzz;
+    T buz = wr * nth - wt * nr_;
+    const T bwr = nth * uz - nzz * ut;
+    const T bwt = nzz * ur - nr_ * uz;
+    const T bwz = nr_ * ut - nth * ur;
+    if (heated) {
+      const C2<T> l3 = buf[3 * ls + a], l4 = buf[4 * ls + a];
+      bur -= ntt * l3.x;
+      but -= ntt * l3.y;
+      buz -= ntt * l4.x;
+      buf[3 * ls + a] = {-ntt * ur, -ntt * ut};
+      buf[4 * ls + a] = {-ntt * uz, T(0)};
+    }
+    buf[a] = {bur, but};
+    buf[ls + a] = {buz, bwr};
+    buf[2 * ls + a] = {bwt, bwz};
+  }
+  __syncthreads();
+  fft_lines<T, false, kMaxB>(buf, npi, ls, pt, tw);
+  for (int idx = threadIdx.x; idx < npi * mt; idx += blockDim.x) {
+    const int p = idx / mt;
+    const int m = idx - p * mt;
+    const C2<T> zm = buf[p * ls + m];
+    const C2<T> zc = buf[p * ls + (m == 0 ? 0 : nt - m)];
+    const C2<T> x = {T(0.5) * (zm.x + zc.x), T(0.5) * (zm.y - zc.y)};
+    const C2<T> y = {T(0.5) * (zm.y + zc.y), T(0.5) * (zc.x - zm.x)};
+    zl[(size_t)(2 * p) * fstride + m] = x;
+    if (2 * p + 1 < n_in) zl[(size_t)(2 * p + 1) * fstride + m] = y;
+  }
+}
+
+// Forward z FFT of the input adjoints, times c_m -> Dbar[n_in][N_r][modes].
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads)
+k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict__ db,
+           const C2<T> *__restrict__ tw, int tm) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  const int nz = d.nz, K = d.kmax, mz = d.mz;
+  const int ls = nz + 1;
+  const int mt0 = blockIdx.x * tm;
+  const int j = blockIdx.y;
+  const int f = blockIdx.z;
+  const int nl = min(tm, d.mt - mt0);
+  const C2<T> *in = Z + ((size_t)f * d.nr + j) * nz * d.mt;
+  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
+    const int b = idx / nl;
+    const int li = idx - b * nl;
+    buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
+  }
+  __syncthreads();
+  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tw);
+  const size_t plane = (size_t)d.nmodes;
+  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
+    const int li = idx / mz;
+    const int kk = idx - li * mz;
+    const int m = mt0 + li;
+    const int k = kk - K;
+    const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
+    const double cm = m == 0 ? 1.0 : 2.0;
+    db[((size_t)f * d.nr + j) * plane + (size_t)m * mz + kk] = make_double2(cm * (double)v.x, cm * (double)v.y);
+  }
+}
+
+// ubar += D(u)^T dbar (transposes of the spectral curl/gradient) + buoyancy.
+__global__ void k_derived_adj(Dims d, Grid g, const double2 *__restrict__ db,
+                              const double2 *__restrict__ nb, double2 *__restrict__ ub) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double ri = g.rinv[j];
+  const double mr = (double)m * ri;
+  auto D = [&](int f) { return db[((size_t)f * n + j) * P + md]; };
+  // (D1^T v)_j over the rows whose window holds j
+  auto D1T = [&](int f) {
+    double2 acc = make_double2(0.0, 0.0);
+    const int lo = j - 8 < 0 ? 0 : j - 8;
+    const int hi = j + 8 > n - 1 ? n - 1 : j + 8;
+    for (int i = lo; i <= hi; ++i) {
+      const int t = j - g.s[i];
+      if (t >= 0 && t < kStencil) {
+        const double w = g.d1[i * kStencil + t];
+        const double2 v = db[((size_t)f * n + i) * P + md];
+        acc.x = fma(w, v.x, acc.x);
+        acc.y = fma(w, v.y, acc.y);
+      }
+    }
+    return acc;
+  };
+  auto mul_i = [](double s, double2 v) { return make_double2(-s * v.y, s * v.x); };  // i s v
+  auto add = [&](int f, double2 v) {
+    double2 *p = ub + ((size_t)f * n + j) * P + md;
+    p->x += v.x;
+    p->y += v.y;
+  };
+  const double2 d0 = D(0), d1 = D(1), d2 = D(2), d3 = D(3), d4 = D(4), d5 = D(5);
+  const double2 a4 = mul_i(-kap, d4), a5 = mul_i(mr, d5);
+  add(0, make_double2(d0.x + a4.x + a5.x, d0.y + a4.y + a5.y));
+  const double2 b3 = mul_i(kap, d3), t5 = D1T(5);
+  add(1, make_double2(d1.x + b3.x + t5.x + ri * d5.x, d1.y + b3.y + t5.y + ri * d5.y));
+  const double2 c3 = mul_i(-mr, d3), t4 = D1T(4);
+  add(2, make_double2(d2.x + c3.x - t4.x, d2.y + c3.y - t4.y));
+  if (d.heated) {
+    const double2 t6 = D1T(6), e7 = mul_i(-mr, D(7)), e8 = mul_i(-kap, D(8));
+    double2 nz = nb[((size_t)2 * n + j) * P + md];
+    if (md < d.mz) {
+      const double2 w = nb[((size_t)2 * n + j) * P + (d.mz - 1 - md)];
+      nz = make_double2(0.5 * (nz.x + w.x), 0.5 * (nz.y - w.y));
+    }
+    add(3, make_double2(t6.x + e7.x + e8.x + d.gr * nz.x, t6.y + e7.y + e8.y + d.gr * nz.y));
+  }
+}
+
 int min_radix(const FftPlan &p) { return p.min_radix; }
 
 // Threads so that nlines * n / min_radix butterflies fit kMaxB per thread,
@@ -354,6 +576,38 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw)
   return hipGetLastError();
 }
 
+
+template <typename T>
+hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *nbar, double *ubar,
+                              const T *twz, const T *twt) {
+  const int tm = z_lines(c, sizeof(C2<T>));
+  const int zthreads = block_for(c->plan_z, tm, 256);
+  const size_t zshm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  // forward fields on the (r, theta-spectral, z-physical) grid
+  hipLaunchKernelGGL(k_zinv<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads), zshm,
+                     c->stream, c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
+                     reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz), tm);
+  const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
+  hipLaunchKernelGGL(k_zinv_adj<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out), dim3(zthreads),
+                     zshm, c->stream, c->d, c->plan_z, reinterpret_cast<const double2 *>(nbar),
+                     reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twz), tm,
+                     scale);
+  const int npi = (c->n_in + 1) / 2;
+  const int tthreads = block_for(c->plan_t, npi + 2, 256);
+  const size_t tshm = (size_t)(npi + 2) * (c->d.nt + 1) * sizeof(C2<T>);
+  hipLaunchKernelGGL(k_theta_adj<T>, dim3(c->d.nz, c->d.nr), dim3(tthreads), tshm, c->stream, c->d,
+                     c->plan_t, reinterpret_cast<C2<T> *>(c->zbuf),
+                     reinterpret_cast<const C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twt),
+                     c->n_in, c->n_out);
+  hipLaunchKernelGGL(k_zfwd_adj<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads),
+                     zshm, c->stream, c->d, c->plan_z, reinterpret_cast<const C2<T> *>(c->zbuf),
+                     reinterpret_cast<double2 *>(c->s_adj), reinterpret_cast<const C2<T> *>(twz), tm);
+  hipLaunchKernelGGL(k_derived_adj, dim3((c->d.nmodes + 255) / 256, c->d.nr), dim3(256), 0, c->stream,
+                     c->d, c->g, reinterpret_cast<const double2 *>(c->s_adj),
+                     reinterpret_cast<const double2 *>(nbar), reinterpret_cast<double2 *>(ubar));
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u) {
@@ -375,6 +629,12 @@ hipError_t launch_cfl_final(const nsc_ctx *c, double *out) {
   hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, c->stream, c->cfl_part,
                      c->cfl_nblk, out);
   return hipGetLastError();
+}
+
+hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, const double *nbar,
+                                double *ubar) {
+  if (prec == NSC_MIXED) return nonlinear_vjp_impl<float>(c, u, nbar, ubar, c->tw32_z, c->tw32_t);
+  return nonlinear_vjp_impl<double>(c, u, nbar, ubar, c->tw64_z, c->tw64_t);
 }
 
 }  // namespace nsc

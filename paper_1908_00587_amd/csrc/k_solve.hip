@@ -671,6 +671,362 @@ __global__ void k_add_base(Dims d, Grid g, const double2 *__restrict__ pert, dou
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector--Jacobian product of the implicit stage (discrete adjoint).  The
+// stage is affine in (X^n, N^n, N^q); its linear part per mode is, in order,
+//   f = X^n/dt + (1-c) L X^n + c N^q + (1-c) N^n   (+- basis)
+//   g = mask(div f), p0 = P^-1 g, X0 = H^-1 mask(f - grad p0),
+//   lambda = -A^-1 beta(X0), X = X0 + sum lambda_j X_j, herm(output).
+// The adjoint applies the transposes in reverse order; complex-linear maps
+// are conjugate-transposed (real factors transpose, i -> -i).
+// ---------------------------------------------------------------------------
+
+// A^T x = b with A = L U in envelope storage: U^T y = b, then L^T x = y.
+template <typename V, typename RHS, typename OUT>
+__device__ __forceinline__ void lu_solve_t(const Factors &F, int op, int n, RHS rhs, OUT out) {
+  const size_t nops = F.nops;
+  const double *vals = F.vals + op;
+  const double *edge = F.edge + op;
+  V yb[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) yb[t] = V{};
+  for (int j = 0; j < n; ++j) {
+    V y = rhs(j);
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) {
+      const int c = j - t;
+      if (c >= 0) y = y - vals[((size_t)c * kSlots + 4 + t) * nops] * yb[t - 1];
+    }
+    if (j <= 8) {
+#pragma unroll
+      for (int b = 5; b <= 8; ++b) {
+        const int c = j - b;
+        if (c >= 0 && c <= 3) y = y - edge[(size_t)(edge_off(c) + j - c - 5) * nops] * yb[b - 1];
+      }
+    }
+    y = vals[((size_t)j * kSlots + 4) * nops] * y;
+#pragma unroll
+    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
+    yb[0] = y;
+    out(j) = y;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) yb[t] = V{};
+  for (int j = n - 1; j >= 0; --j) {
+    V x = out(j);
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) {
+      const int c = j + t;
+      if (c < n) x = x - vals[((size_t)c * kSlots + 4 - t) * nops] * yb[t - 1];
+    }
+    if (j >= n - 9) {
+#pragma unroll
+      for (int b = 5; b <= 8; ++b) {
+        const int c = j + b;
+        if (c <= n - 1 && c >= n - 4)
+          x = x - edge[(size_t)(10 + edge_off(n - 1 - c) + j - (n - 9)) * nops] * yb[b - 1];
+      }
+    }
+#pragma unroll
+    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
+    yb[0] = x;
+    out(j) = x;
+  }
+}
+
+// (W^T v)_j = sum_i W[i][j - s_i] v_i over the rows i whose window holds j.
+__device__ __forceinline__ Cd wt_rowc(const Grid &g, const double *w, int n, int j,
+                                      const double2 *v, size_t stride, bool scale_rinv) {
+  Cd acc = {0, 0};
+  const int lo = j - 8 < 0 ? 0 : j - 8;
+  const int hi = j + 8 > n - 1 ? n - 1 : j + 8;
+  for (int i = lo; i <= hi; ++i) {
+    const int s = g.s[i];
+    const int t = j - s;
+    if (t >= 0 && t < kStencil) {
+      double c = w[i * kStencil + t];
+      if (scale_rinv) c *= g.rinv[i];
+      acc = fmac(c, ld(v + (size_t)i * stride), acc);
+    }
+  }
+  return acc;
+}
+
+// Output adjoint: Hermitian projection of u_bar, then the +- basis:
+// Xbar+- = (ubar_r +- i ubar_theta)/2, Xbar_z = ubar_z, Tbar.  Mode (0,0)
+// keeps ubar_theta in slot 0 (its u_theta is solved directly).
+__global__ void k_adj_out(Dims d, const double2 *__restrict__ ub, double2 *__restrict__ sx) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  auto U = [&](int f, int m2) { return ld(ub + ((size_t)f * n + j) * P + m2); };
+  Cd v[4];
+  for (int f = 0; f < d.f; ++f) {
+    v[f] = U(f, md);
+    if (md < d.mz) {
+      const Cd w = U(f, d.mz - 1 - md);
+      v[f] = {0.5 * (v[f].x + w.x), 0.5 * (v[f].y - w.y)};
+    }
+  }
+  if (md == d.kmax) {
+    st(sx + ((size_t)0 * n + j) * P + md, v[1]);
+    st(sx + ((size_t)1 * n + j) * P + md, Cd{0, 0});
+  } else {
+    st(sx + ((size_t)0 * n + j) * P + md, 0.5 * (v[0] + ci(v[1])));
+    st(sx + ((size_t)1 * n + j) * P + md, 0.5 * (v[0] - ci(v[1])));
+  }
+  st(sx + ((size_t)2 * n + j) * P + md, v[2]);
+  if (d.heated) st(sx + ((size_t)3 * n + j) * P + md, v[3]);
+}
+
+// lambda_bar_j = sum_r (X_j+ Xbar+ + X_j- Xbar- + i kappa h_j Xbar_z);
+// beta_bar = -A^-T lambda_bar.
+__global__ void k_adj_lambda(Dims d, Influence I, const double2 *__restrict__ sx,
+                             double2 *__restrict__ bbar) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  if (m == 0 && ka == 0) {
+    st(bbar + 2 * (size_t)md, Cd{0, 0});
+    st(bbar + 2 * (size_t)md + 1, Cd{0, 0});
+    return;
+  }
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const int op = m * kp1 + ka;
+  const size_t ns = I.nops;
+  Cd l1 = {0, 0}, l2 = {0, 0};
+  for (int j = 0; j < n; ++j) {
+    const Cd xp = ld(sx + (size_t)j * P + md);
+    const Cd xm = ld(sx + ((size_t)n + j) * P + md);
+    const Cd xz = kap * ci(ld(sx + ((size_t)2 * n + j) * P + md));  // i kappa Xbar_z
+    auto Rv = [&](int s) { return I.resp[((size_t)s * n + j) * ns + op]; };
+    l1 = l1 + (Rv(2) * xp + Rv(4) * xm + Rv(6) * xz);
+    l2 = l2 + (Rv(3) * xp + Rv(5) * xm + Rv(7) * xz);
+  }
+  const double a00 = I.ainv[op], a01 = I.ainv[ns + op], a10 = I.ainv[2 * ns + op], a11 = I.ainv[3 * ns + op];
+  st(bbar + 2 * (size_t)md, Cd{-(a00 * l1.x + a10 * l2.x), -(a00 * l1.y + a10 * l2.y)});
+  st(bbar + 2 * (size_t)md + 1, Cd{-(a01 * l1.x + a11 * l2.x), -(a01 * l1.y + a11 * l2.y)});
+}
+
+// Transposed Helmholtz sweeps: comp 0/1/2 velocity (+, -, z), 3 temperature.
+// rbar = mask(H^-T (Xbar + beta terms)) -> sf[comp]; mode (0,0) is the
+// direct u_theta / u_z problem.
+__global__ void __launch_bounds__(256)
+k_adj_vel(Dims d, Grid g, Factors fv, Factors ft, const double2 *__restrict__ sx,
+          const double2 *__restrict__ bbar, double2 *__restrict__ sf) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const int comp = blockIdx.y;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const bool zero = (m == 0 && ka == 0);
+  const double2 *xb = sx + (size_t)comp * n * P + md;
+  double2 *out = sf + (size_t)comp * n * P + md;
+  auto outr = [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(out + (size_t)j * P); };
+  if (comp == 3) {
+    lu_solve_t<Cd>(ft, m * kp1 + ka, n, [&](int j) { return ld(xb + (size_t)j * P); }, outr);
+    outr(0) = Cd{0, 0};
+    outr(n - 1) = Cd{0, 0};
+    return;
+  }
+  if (zero) {
+    if (comp == 1) return;
+    const int q = comp == 0 ? 1 : 0;
+    lu_solve_t<Cd>(fv, q * kp1 + ka, n, [&](int j) { return ld(xb + (size_t)j * P); }, outr);
+    outr(0) = Cd{0, 0};
+    outr(n - 1) = Cd{0, 0};
+    if (comp == 0) {  // fbar+ = (i/2) rbar_theta, fbar- = -(i/2) rbar_theta
+      double2 *om = sf + (size_t)n * P + md;
+      for (int j = 0; j < n; ++j) {
+        const Cd r = outr(j);
+        const Cd h = 0.5 * ci(r);
+        outr(j) = h;
+        st(om + (size_t)j * P, Cd{-h.x, -h.y});
+      }
+    }
+    return;
+  }
+  const int q = comp == 0 ? m + 1 : (comp == 1 ? (m >= 1 ? m - 1 : 1 - m) : m);
+  const Cd b0 = ld(bbar + 2 * (size_t)md), b1 = ld(bbar + 2 * (size_t)md + 1);
+  const double sgn = comp == 0 ? 1.0 : -1.0;
+  auto rhs = [&](int j) -> Cd {
+    Cd v = ld(xb + (size_t)j * P);
+    if (comp < 2) {
+      // 1/2 (D1 + (1 +- m)/r)^T e_w beta_bar_w
+      if (j <= 8) {
+        double c = g.d1[0 * kStencil + j];
+        if (j == 0) c += (1.0 + sgn * m) * g.rinv[0];
+        v = v + (0.5 * c) * b0;
+      }
+      if (j >= n - 9) {
+        double c = g.d1[(n - 1) * kStencil + (j - g.s[n - 1])];
+        if (j == n - 1) c += (1.0 + sgn * m) * g.rinv[n - 1];
+        v = v + (0.5 * c) * b1;
+      }
+    } else {
+      if (j == 0) v = v - kap * ci(b0);
+      if (j == n - 1) v = v - kap * ci(b1);
+    }
+    return v;
+  };
+  lu_solve_t<Cd>(fv, q * kp1 + ka, n, rhs, outr);
+  outr(0) = Cd{0, 0};
+  outr(n - 1) = Cd{0, 0};
+}
+
+// pbar0 = -D1^T (rbar+ + rbar-) + (m/r)(rbar+ - rbar-) + i kappa rbar_z.
+__global__ void k_adj_pbar(Dims d, Grid g, const double2 *__restrict__ sf, double2 *__restrict__ pb) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  if (md == d.kmax) {
+    st(pb + (size_t)j * P + md, Cd{0, 0});
+    return;
+  }
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double2 *rp = sf + md, *rm = sf + (size_t)n * P + md, *rz = sf + (size_t)2 * n * P + md;
+  const Cd dp = wt_rowc(g, g.d1, n, j, rp, P, false);
+  const Cd dm = wt_rowc(g, g.d1, n, j, rm, P, false);
+  const Cd vp = ld(rp + (size_t)j * P), vm = ld(rm + (size_t)j * P), vz = ld(rz + (size_t)j * P);
+  const Cd res = ((m * g.rinv[j]) * (vp - vm)) - (dp + dm) + kap * ci(vz);
+  st(pb + (size_t)j * P + md, res);
+}
+
+// gbar = mask(P^-T pbar0).
+__global__ void __launch_bounds__(256)
+k_adj_poisson(Dims d, Factors fp, const double2 *__restrict__ pb, double2 *__restrict__ gb) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  auto outr = [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(gb + (size_t)j * P + md); };
+  if (m == 0 && ka == 0) {
+    for (int j = 0; j < n; ++j) outr(j) = Cd{0, 0};
+    return;
+  }
+  lu_solve_t<Cd>(fp, m * kp1 + ka, n, [&](int j) { return ld(pb + (size_t)j * P + md); }, outr);
+  outr(0) = Cd{0, 0};
+  outr(n - 1) = Cd{0, 0};
+}
+
+// fbar+- = rbar+- + 1/2 (D1^T gbar + (1 +- m) gbar / r), fbar_z = rbar_z - i kappa gbar.
+__global__ void k_adj_f(Dims d, Grid g, const double2 *__restrict__ sf, const double2 *__restrict__ gb,
+                        double2 *__restrict__ fb) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  Cd fp = ld(sf + (size_t)j * P + md), fm = ld(sf + ((size_t)n + j) * P + md);
+  Cd fz = ld(sf + ((size_t)2 * n + j) * P + md);
+  if (md != d.kmax) {
+    const Cd dg = wt_rowc(g, g.d1, n, j, gb + md, P, false);
+    const Cd gv = ld(gb + (size_t)j * P + md);
+    const double ri = g.rinv[j];
+    fp = fp + 0.5 * (dg + ((1.0 + m) * ri) * gv);
+    fm = fm + 0.5 * (dg + ((1.0 - m) * ri) * gv);
+    fz = fz - kap * ci(gv);
+  }
+  st(fb + (size_t)j * P + md, fp);
+  st(fb + ((size_t)n + j) * P + md, fm);
+  st(fb + ((size_t)2 * n + j) * P + md, fz);
+  if (d.heated) st(fb + ((size_t)3 * n + j) * P + md, ld(sf + ((size_t)3 * n + j) * P + md));
+}
+
+// Input adjoints: Xbar^n = fbar/dt + (1-c) L^T fbar; Nbar^q = c fbar,
+// Nbar^n = (1-c) fbar; back to (r, theta, z, T) and accumulated.
+__global__ void __launch_bounds__(256)
+k_adj_in(Dims d, Grid g, const double2 *__restrict__ fb, double idt, double cc,
+         double2 *__restrict__ ubn, double2 *__restrict__ nbn, double2 *__restrict__ nbq) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double ri = g.rinv[j], r2 = ri * ri, k2 = kap * kap;
+  const double ce = 1.0 - cc;
+  Cd xb[4], fv[4];
+  const int nf = d.heated ? 4 : 3;
+  for (int c = 0; c < nf; ++c) {
+    const double2 *f = fb + (size_t)c * n * P + md;
+    const double q = c == 0 ? (double)(m + 1) : (c == 1 ? (double)(m >= 1 ? m - 1 : 1 - m) : (double)m);
+    const Cd v = ld(f + (size_t)j * P);
+    const Cd LT = wt_rowc(g, g.d2, n, j, f, P, false) + wt_rowc(g, g.d1, n, j, f, P, true) -
+                  (q * q * r2 + k2) * v;
+    const double sc = c == 3 ? ce / d.pr : ce;
+    xb[c] = idt * v + sc * LT;
+    fv[c] = v;
+  }
+  auto acc = [&](double2 *base, int f, Cd v) {
+    double2 *p = base + ((size_t)f * n + j) * P + md;
+    p->x += v.x;
+    p->y += v.y;
+  };
+  // X+- = X_r +- i X_theta  =>  Xbar_r = Xbar+ + Xbar-, Xbar_theta = -i (Xbar+ - Xbar-)
+  const Cd ur = xb[0] + xb[1];
+  const Cd dd = xb[0] - xb[1];
+  const Cd ut = {dd.y, -dd.x};
+  acc(ubn, 0, ur);
+  acc(ubn, 1, ut);
+  acc(ubn, 2, xb[2]);
+  if (d.heated) acc(ubn, 3, xb[3]);
+  const Cd fr = fv[0] + fv[1];
+  const Cd fdd = fv[0] - fv[1];
+  const Cd ft = {fdd.y, -fdd.x};
+  acc(nbq, 0, cc * fr);
+  acc(nbq, 1, cc * ft);
+  acc(nbq, 2, cc * fv[2]);
+  acc(nbn, 0, ce * fr);
+  acc(nbn, 1, ce * ft);
+  acc(nbn, 2, ce * fv[2]);
+  if (d.heated) {
+    acc(nbq, 3, cc * fv[3]);
+    acc(nbn, 3, ce * fv[3]);
+  }
+}
+
+// dE/du = 2 pi L_z w_j r_j c_m (u - U_b) for the velocity, 0 for T.
+__global__ void k_energy_grad(Dims d, Grid g, const double2 *__restrict__ u, double2 *__restrict__ gout) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int m = md / d.mz;
+  const double s = 2.0 * M_PI * d.lz * g.ccw[j] * g.r[j] * (m == 0 ? 1.0 : 2.0);
+  for (int f = 0; f < d.f; ++f) {
+    double2 v = u[((size_t)f * d.nr + j) * P + md];
+    if (f == 1 && md == d.kmax) v.x -= d.a_cou * g.r[j] + d.b_cou * g.rinv[j];
+    if (f == 3) v = make_double2(0.0, 0.0);
+    gout[((size_t)f * d.nr + j) * P + md] = make_double2(s * v.x, s * v.y);
+  }
+}
+
 inline dim3 mode_grid(const nsc_ctx *c, int y, int z = 1) {
   return dim3((c->d.nmodes + 255) / 256, y, z);
 }
@@ -755,6 +1111,33 @@ hipError_t launch_seed(const nsc_ctx *c, const double *amps, double *out_pert) {
 hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *out) {
   hipLaunchKernelGGL(k_add_base, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
                      reinterpret_cast<const double2 *>(pert_tilde), reinterpret_cast<double2 *>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ubar_n,
+                            double *nbar_n, double *nbar_q, double dt, double cc) {
+  const double2 *ub = reinterpret_cast<const double2 *>(ubar_out);
+  double2 *sx = reinterpret_cast<double2 *>(c->s_x);
+  double2 *sf = reinterpret_cast<double2 *>(c->s_f);
+  double2 *sg = reinterpret_cast<double2 *>(c->s_g);
+  double2 *sp = reinterpret_cast<double2 *>(c->s_p);
+  double2 *lam = reinterpret_cast<double2 *>(c->s_lam);
+  hipLaunchKernelGGL(k_adj_out, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, ub, sx);
+  hipLaunchKernelGGL(k_adj_lambda, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->inf, sx, lam);
+  hipLaunchKernelGGL(k_adj_vel, mode_grid(c, c->d.heated ? 4 : 3), dim3(256), 0, c->stream, c->d, c->g,
+                     c->fv, c->ft, sx, lam, sf);
+  hipLaunchKernelGGL(k_adj_pbar, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sp);
+  hipLaunchKernelGGL(k_adj_poisson, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->fp, sp, sg);
+  hipLaunchKernelGGL(k_adj_f, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sg, sx);
+  hipLaunchKernelGGL(k_adj_in, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sx, 1.0 / dt,
+                     cc, reinterpret_cast<double2 *>(ubar_n), reinterpret_cast<double2 *>(nbar_n),
+                     reinterpret_cast<double2 *>(nbar_q));
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout) {
+  hipLaunchKernelGGL(k_energy_grad, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(gout));
   return hipGetLastError();
 }
 

@@ -262,7 +262,7 @@ int nsc_destroy(nsc_ctx *c) {
   if (!c) return NSC_OK;
   void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
                   c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
-                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->inf.resp, c->inf.ainv};
+                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->inf.resp, c->inf.ainv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_factors(&c->fv);
@@ -400,6 +400,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   TRY(dmalloc((void **)&c->s_nn, field * d.f));
   TRY(dmalloc((void **)&c->s_nq, field * d.f));
   TRY(dmalloc((void **)&c->s_tmp, field * d.f));
+  TRY(dmalloc((void **)&c->s_adj, field * c->n_in));
   HIPCHK(hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault));
   HIPCHK(hipEventCreateWithFlags(&c->ev_cfl, hipEventDisableTiming));
   HIPCHK(hipEventCreate(&c->ev0));
@@ -525,6 +526,32 @@ int nsc_initial_state(nsc_ctx *c, const double *amps, double *out) {
   HIPCHK(launch_seed(c, amps, c->s_tmp));
   TRY(solve_impl(c, c->s_tmp, nullptr, nullptr, out, nullptr, 1e-3, 1.0, 0));
   HIPCHK(launch_add_base(c, c->s_tmp, out));
+  return NSC_OK;
+}
+
+int nsc_nonlinear_vjp(nsc_ctx *c, const double *u, const double *nbar, double *ubar) {
+  if (!c || !u || !nbar || !ubar) return NSC_ERR_ARG;
+  if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)nbar)
+    return NSC_ERR_ARG;
+  HIPCHK(launch_nonlinear_vjp(c, c->precision, u, nbar, ubar));
+  return NSC_OK;
+}
+
+int nsc_radial_solve_vjp(nsc_ctx *c, const double *ubar_out, double *ubar_n, double *nbar_n,
+                         double *nbar_q) {
+  if (!c || !ubar_out || !ubar_n || !nbar_n || !nbar_q) return NSC_ERR_ARG;
+  const void *o = ubar_out;
+  if (o == ubar_n || o == nbar_n || o == nbar_q || (void *)ubar_n == (void *)nbar_n ||
+      (void *)ubar_n == (void *)nbar_q || (void *)nbar_n == (void *)nbar_q)
+    return NSC_ERR_ARG;
+  TRY(ensure_factors(c, c->dt, c->c));
+  HIPCHK(launch_solve_vjp(c, ubar_out, ubar_n, nbar_n, nbar_q, c->dt, c->c));
+  return NSC_OK;
+}
+
+int nsc_energy_grad(nsc_ctx *c, const double *u, double *g) {
+  if (!c || !u || !g || (const void *)u == (const void *)g) return NSC_ERR_ARG;
+  HIPCHK(launch_energy_grad(c, u, g));
   return NSC_OK;
 }
 

@@ -103,6 +103,7 @@ struct nsc_ctx {
   double *s_nn = nullptr;   // [F][N_r][modes] complex N^n
   double *s_nq = nullptr;   // [F][N_r][modes] complex N^q
   double *s_tmp = nullptr;  // [F][N_r][modes] complex scratch
+  double *s_adj = nullptr;  // [n_in][N_r][modes] complex adjoint of the derived fields
   double *h_pinned = nullptr;  // pinned host scalar(s)
   hipEvent_t ev_cfl = nullptr;
   // profiling
@@ -134,6 +135,11 @@ hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out);
 hipError_t launch_energy(const nsc_ctx *c, const double *u, double *e_dev);
 hipError_t launch_seed(const nsc_ctx *c, const double *amps, double *out_pert);
 hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *out);
+hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ubar_n,
+                            double *nbar_n, double *nbar_q, double dt, double cc);
+hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout);
+hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, const double *nbar,
+                                double *ubar);
 
 // operator kinds for launch_factor
 enum { OP_HELMHOLTZ = 0, OP_POISSON = 1, OP_MEAN_PRESSURE = 2 };

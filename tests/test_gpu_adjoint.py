@@ -1,0 +1,140 @@
+"""GPU discrete adjoint: dot-product tests of each vector--Jacobian product
+(through the C ABI), the rollout gradient against the oracle's autograd
+gradient, and against central finite differences."""
+import math
+import sys
+
+import pytest
+import torch
+
+import oracle as O
+from synthetic import direction, mode_amplitudes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _inner(a, b):
+    return float((a.conj() * b).real.sum())
+
+
+CASES = {
+    "tiny": (0.5, 50.0, 0.0, 0.0, 1.0, 12, 4, 7, 2 * math.pi),
+    "heated": (0.71, 100.0, 0.0, 1.0e4, 0.7, 16, 8, 15, 2 * math.pi),
+    "ragged": (0.6, 80.0, 10.0, 0.0, 1.0, 13, 5, 9, 4.0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_radial_solve_vjp_dot(case):
+    _say("solve vjp dot", case)
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import radial_solve_vjp
+    args = CASES[case]
+    p = O.Params(*args)
+    ctx = nsc.Context(*args)
+    ctx.set_timestep(dt=1e-3, c=0.5)
+    sh = (p.F, p.N_r, p.M_theta, p.M_z)
+    dX, dA, dB, ub = [direction(*sh, seed=s).cuda() for s in (31, 32, 33, 34)]
+    z = torch.zeros_like(dX)
+    s0 = ctx.radial_solve(z, z, z)
+    s1 = ctx.radial_solve(dX, dA, dB)
+    lhs = _inner(ub, s1 - s0)
+    xb, ab, bb = radial_solve_vjp(ctx, ub)
+    rhs = _inner(xb, dX) + _inner(ab, dA) + _inner(bb, dB)
+    torch.cuda.synchronize()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs), (lhs, rhs)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nonlinear_vjp_dot(case):
+    """N is quadratic (plus linear buoyancy), so the central difference
+    (N(u+d) - N(u-d))/2 is the exact Jacobian action."""
+    _say("nonlinear vjp dot", case)
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import nonlinear_vjp
+    args = CASES[case]
+    p = O.Params(*args)
+    ctx = nsc.Context(*args)
+    sh = (p.F, p.N_r, p.M_theta, p.M_z)
+    u = (O.base_state(p) + 1e-2 * direction(*sh, seed=41)).cuda()
+    d = (1e-1 * direction(*sh, seed=42)).cuda()
+    nb = direction(*sh, seed=43).cuda()
+    jd = 0.5 * (ctx.nonlinear(u + d) - ctx.nonlinear(u - d))
+    lhs = _inner(nb, jd)
+    rhs = _inner(nonlinear_vjp(ctx, u, nb), d)
+    torch.cuda.synchronize()
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs), (lhs, rhs)
+
+
+def test_energy_grad_matches_oracle_autograd():
+    _say("energy grad")
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import energy_grad
+    args = CASES["heated"]
+    p = O.Params(*args)
+    u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 51)
+    x = u.clone().requires_grad_(True)
+    O.energy(p, x).backward()
+    ctx = nsc.Context(*args)
+    g = energy_grad(ctx, u.cuda()).cpu()
+    assert float((g - x.grad).abs().max()) <= 1e-12 * float(x.grad.abs().max())
+
+
+@pytest.mark.parametrize("case,steps,ckpt", [("tiny", 6, 4), ("heated", 4, 2)])
+def test_rollout_gradient_matches_oracle_autograd(case, steps, ckpt):
+    _say("rollout gradient", case)
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout_energy
+    args = CASES[case]
+    p = O.Params(*args)
+    u0 = O.initial_state(p, mode_amplitudes(p.F, p.M_theta, p.M_z, 1e-2, seed=1000))
+    dt = 1e-3
+    x = u0.clone().requires_grad_(True)
+    uS, _ = O.run(p, x, steps, dt0=dt)
+    O.energy(p, uS).backward()
+    ctx = nsc.Context(*args)
+    y = u0.cuda().requires_grad_(True)
+    e = rollout_energy(ctx, y, steps, dt, ckpt_every=ckpt)
+    e.backward()
+    torch.cuda.synchronize()
+    g = y.grad.cpu()
+    assert float((g - x.grad).abs().max()) <= 1e-10 * float(x.grad.abs().max())
+
+
+def test_rollout_gradient_finite_differences_adjoint_workload():
+    """Adjoint workload (eta = 0.71, Re_i = 200, N_r = 64, 32 x 63 modes,
+    200 steps at dt = 5e-4, checkpoint every 20): gradient vs FP64 central
+    differences along 8 seeded directions."""
+    _say("FD adjoint workload")
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout, rollout_energy
+    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+    name = "tc-adjoint-n64"
+    w = WORKLOADS[name]
+    ctx = nsc.Context(*params(name))
+    amps = amplitudes(name).cuda()
+    u0 = ctx.initial_state(amps)
+    pert_norm = float(torch.linalg.vector_norm(u0 - ctx.initial_state(0 * amps)))
+    steps, dt = w["steps"], w["dt"]
+    y = u0.clone().requires_grad_(True)
+    e = rollout_energy(ctx, y, steps, dt, ckpt_every=20)
+    e.backward()
+    g = y.grad
+    ctx.set_timestep(dt=dt)
+    worst = 0.0
+    for s in range(2000, 2008):
+        d = direction(ctx.F, ctx.N_r, ctx.M_theta, ctx.M_z, s).cuda()
+        d = d * (1e-3 * pert_norm / float(torch.linalg.vector_norm(d)))
+        eps = 1.0
+        ep = float(ctx.energy(rollout(ctx, u0 + eps * d, steps, dt)).cpu()[0])
+        em = float(ctx.energy(rollout(ctx, u0 - eps * d, steps, dt)).cpu()[0])
+        fd = (ep - em) / (2 * eps)
+        an = _inner(g, d)
+        worst = max(worst, abs(fd - an) / abs(fd))
+        _say(f"dir {s}: fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(fd):.2e}")
+    assert worst <= 1e-6

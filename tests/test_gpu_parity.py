@@ -95,22 +95,39 @@ def test_initial_state_and_energy(case):
     assert rel(ctx.grid(), O.radial_grid(p)) < 1e-15
 
 
-@pytest.mark.parametrize("case,steps", [("tiny", 10), ("heated", 5), ("iso32", 100)])
+@pytest.mark.parametrize("case,steps", [("tiny", 10), ("heated", 10), ("iso32", 100)])
 def test_step_fp64(case, steps):
+    """Per-step (local) error: every GPU step taken from the oracle's state
+    matches the oracle's next state to 1e-12 per field; the trajectory
+    (global) error after `steps` steps stays below 1e-10 per field (rounding
+    differences of the two LU orderings accumulate, see the tolerance
+    derivation)."""
     _say("step", case, steps)
     args = CASES[case]
     p = O.Params(*args)
     u0 = O.initial_state(p, mode_amplitudes(p.F, p.M_theta, p.M_z, 1e-3, seed=1000))
     dt = 1e-3
-    ref, _ = O.run(p, u0, steps, dt0=dt)
+    states = [u0]
+    for _ in range(steps):
+        states.append(O.step(p, states[-1], dt)[0])
     ctx = _nsc().Context(*args)
     ctx.set_timestep(dt=dt)
+    worst = [0.0] * p.F
+    for n in range(steps):
+        x = states[n].cuda()
+        ctx.step(x, dt)
+        x = x.cpu()
+        for f in range(p.F):
+            worst[f] = max(worst[f], rel(x[f], states[n + 1][f]))
+    _say("  local per-step max rel err per field", worst)
+    assert max(worst) < TOL64
     u = u0.cuda()
     for _ in range(steps):
         ctx.step(u, dt)
     torch.cuda.synchronize()
-    for f in range(p.F):
-        assert rel(u[f], ref[f]) < TOL64, f
+    glob = [rel(u[f], states[-1][f]) for f in range(p.F)]
+    _say("  global rel err per field", glob)
+    assert max(glob) < 1e-10
 
 
 def test_dynamic_dt_matches_oracle():
@@ -132,3 +149,41 @@ def test_dynamic_dt_matches_oracle():
     torch.cuda.synchronize()
     assert all(abs(a - b) <= 1e-14 * b for a, b in zip(got, dts))
     assert rel(u, ref) < TOL64
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged", "heated", "iso32"])
+def test_nonlinear_mixed(case):
+    """FP32 transforms/products: error relative to the largest entry of N."""
+    _say("nonlinear mixed", case)
+    args = CASES[case]
+    p = O.Params(*args)
+    u = _rand_state(p, 61)
+    ref, dtc = O.nonlinear(p, u)
+    ctx = _nsc().Context(*args)
+    ctx.set_precision("mixed")
+    out, c = ctx.nonlinear(u.cuda(), cfl=True)
+    torch.cuda.synchronize()
+    assert rel(out, ref) < 2e-6
+    assert abs(float(c.cpu()[0]) - dtc) <= 1e-6 * dtc
+
+
+@pytest.mark.parametrize("case,steps", [("heated", 20), ("iso32", 50)])
+def test_step_mixed_error_stated(case, steps):
+    """Mixed-precision stepping stays within 1e-5 of the FP64 oracle per field."""
+    _say("step mixed", case, steps)
+    args = CASES[case]
+    p = O.Params(*args)
+    u0 = O.initial_state(p, mode_amplitudes(p.F, p.M_theta, p.M_z, 1e-3, seed=1000))
+    dt = 1e-3
+    ref, _ = O.run(p, u0, steps, dt0=dt)
+    ctx = _nsc().Context(*args)
+    ctx.set_precision("mixed")
+    ctx.set_timestep(dt=dt)
+    u = u0.cuda()
+    for _ in range(steps):
+        ctx.step(u, dt)
+    torch.cuda.synchronize()
+    for f in range(p.F):
+        err = rel(u[f], ref[f])
+        _say(f"  field {f}: mixed rel err {err:.2e}")
+        assert err < 1e-5, f
