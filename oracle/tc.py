@@ -247,12 +247,24 @@ def _spacings(p, r):
     return dr
 
 
-def nonlinear_planes(p, u, rows, D1=None, r=None):
-    """Nonlinear term at the radial rows ``rows``.
+def base_profiles(p, r, D1):
+    """Radial profiles of the basic state: V = A r + B/r (Couette), its
+    discrete axial vorticity Om = D1 V + V/r, and the discrete radial
+    gradient G = D1 T_b of the conduction profile (zero if isothermal)."""
+    V = p.A * r + p.B / r
+    Om = D1 @ V + V / r
+    if p.heated:
+        Tb = 0.5 + torch.log(r / p.r_i) / math.log(p.eta)
+        G = D1 @ Tb
+    else:
+        G = torch.zeros_like(r)
+    return V, Om, G
 
-    Returns (Nhat [F][len(rows)][M_theta][M_z], dt_cfl over those rows).
-    Nhat = (u x omega)^ for the velocity, (-u . grad T)^ for T, and
-    Nhat_z += Gr That (buoyancy)."""
+
+def nonlinear_planes_direct(p, u, rows, D1=None, r=None):
+    """Plain definition of the nonlinear term at the radial rows ``rows``:
+    transform u, omega and grad T of the full state, form u x omega and
+    -u . grad T on the padded grid, transform back; N_z += Gr T."""
     if r is None:
         r = radial_grid(p)
     if D1 is None:
@@ -261,18 +273,58 @@ def nonlinear_planes(p, u, rows, D1=None, r=None):
     spec = derived_fields(p, u, D1, r, rows)
     phys = to_physical(p, spec)  # [n][R][N_theta][N_z]
     ur, ut, uz, wr, wt, wz = phys[:6]
-    n_r = ut * wz - uz * wt
-    n_t = uz * wr - ur * wz
-    n_z = ur * wt - ut * wr
-    outs = [n_r, n_t, n_z]
+    outs = [ut * wz - uz * wt, uz * wr - ur * wz, ur * wt - ut * wr]
     if p.heated:
         gr, gt, gz = phys[6:9]
         outs.append(-(ur * gr + ut * gt + uz * gz))
     Nhat = to_spectral(p, torch.stack(outs))
     if p.heated:
         Nhat[2] = Nhat[2] + p.Gr * u[3][rows]
-    # CFL time-step bound on the padded grid
+    return Nhat
+
+
+def nonlinear_planes(p, u, rows, D1=None, r=None):
+    """Nonlinear term at the radial rows ``rows``, evaluated with the exact
+    split u = U_b + u' about the basic state (Couette flow, conduction
+    profile), which depends on r only:
+      u x omega = U_b x Omega_b + U_b x omega' + u' x Omega_b + u' x omega',
+      -u . grad T = -U_b . grad T' - u' . grad T_b - u' . grad T'.
+    Products with the r-only basic state multiply every Fourier coefficient
+    by a radial profile (no new modes, nothing to dealias); only the
+    perturbation products go through the padded grid.  Equal to
+    nonlinear_planes_direct in exact arithmetic; the rounding errors scale
+    with the perturbation instead of the basic state.
+
+    Returns (Nhat [F][len(rows)][M_theta][M_z], dt_cfl over those rows)."""
+    if r is None:
+        r = radial_grid(p)
+    if D1 is None:
+        D1, _ = fd_matrices(p, r)
+    rows = torch.as_tensor(rows)
+    up = u - base_state(p, r)
+    spec = derived_fields(p, up, D1, r, rows)
+    phys = to_physical(p, spec)  # [n][R][N_theta][N_z]
+    ur, ut, uz, wr, wt, wz = phys[:6]
+    outs = [ut * wz - uz * wt, uz * wr - ur * wz, ur * wt - ut * wr]
+    if p.heated:
+        gr, gt, gz = phys[6:9]
+        outs.append(-(ur * gr + ut * gt + uz * gz))
+    Nhat = to_spectral(p, torch.stack(outs))
+    V, Om, G = base_profiles(p, r, D1)
+    Vr = V[rows][:, None, None].to(C128)
+    Omr = Om[rows][:, None, None].to(C128)
+    Nhat[0] = Nhat[0] + Vr * spec[5] + Omr * spec[1]
+    Nhat[1] = Nhat[1] - Omr * spec[0]
+    Nhat[2] = Nhat[2] - Vr * spec[3]
+    Nhat[0, :, 0, p.K] = Nhat[0, :, 0, p.K] + (V * Om)[rows]
+    if p.heated:
+        m, _ = _modes(p)
+        imr = 1j * m[None, :, None] / r[rows][:, None, None]
+        Nhat[3] = Nhat[3] - Vr * imr * up[3][rows] - G[rows][:, None, None].to(C128) * spec[0]
+        Nhat[2] = Nhat[2] + p.Gr * u[3][rows]
+    # CFL time-step bound on the padded grid, from the full velocity
     rr = r[rows][:, None, None]
+    ut = ut + V[rows][:, None, None]
     dr = _spacings(p, r)[rows][:, None, None]
     dth = 2.0 * math.pi / p.N_theta
     dz = p.L_z / p.N_z
@@ -545,11 +597,15 @@ def step(p, u, dt, c=0.5, n_corr=1):
 
 
 def next_dt(dt, dt_cfl, cfl=0.5, dt_max=1e-3):
-    """Dynamic time-step control: candidate min(dt_max, cfl*dt_cfl); accept it
-    when it shrinks the step or grows it by more than 10 %, else keep dt."""
-    cand = min(dt_max, cfl * dt_cfl)
-    if cand < dt or cand > 1.1 * dt:
-        return cand
+    """Dynamic time-step control with hysteresis: the bound is
+    b = cfl * dt_cfl.  If b < dt the step shrinks to 0.9 b; if
+    min(dt_max, b) > 1.2 dt it grows to min(dt_max, 0.9 b); otherwise dt is
+    kept (so the radial operators are refactorised only on real changes)."""
+    b = cfl * dt_cfl
+    if b < dt:
+        return 0.9 * b
+    if min(dt_max, b) > 1.2 * dt:
+        return min(dt_max, 0.9 * b)
     return dt
 
 

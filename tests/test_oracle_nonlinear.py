@@ -5,6 +5,7 @@ import math
 import torch
 
 import oracle as O
+from synthetic import direction
 
 
 def test_rigid_rotation_centripetal_term_exact():
@@ -89,3 +90,36 @@ def test_nonlinear_planes_consistent_with_full():
     N, _ = O.nonlinear(p, u)
     Np, _ = O.nonlinear_planes(p, u, [0, 5, 11])
     assert float((O.herm(p, Np) - N[:, [0, 5, 11]]).abs().max()) < 1e-12 * float(N.abs().max())
+
+
+def test_split_equals_direct_definition():
+    """The basic-state split is exact algebra: it reproduces the plain
+    transform-everything definition to rounding."""
+    for Ra in (0.0, 2.0e3):
+        p = O.Params(0.6, 80.0, -20.0, Ra, 0.7, 14, 5, 9, 3.0)
+        u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 71)
+        rows = torch.arange(p.N_r)
+        Ns, _ = O.nonlinear_planes(p, u, rows)
+        Nd = O.nonlinear_planes_direct(p, u, rows)
+        assert float((Ns - Nd).abs().max()) < 1e-12 * float(Nd.abs().max())
+
+
+def test_split_rounding_scales_with_the_perturbation():
+    """For u = U_b +- eps d the central difference isolates the linear
+    response exactly (N is quadratic); with the split its value does not
+    depend on eps down to eps = 1e-8, i.e. the rounding error is relative to
+    the perturbation, not to the O(Re^2) basic-state term."""
+    p = O.Params(0.71, 2000.0, -1000.0, 0.0, 1.0, 16, 6, 11, 2 * math.pi)
+    ub = O.base_state(p)
+    d = direction(p.F, p.N_r, p.M_theta, p.M_z, 72)
+    d[:, :, 0, p.K] = 0  # so that (U_b + eps d) - U_b = eps d exactly
+    rows = torch.arange(p.N_r)
+
+    def lin(eps):
+        a, _ = O.nonlinear_planes(p, ub + eps * d, rows)
+        b, _ = O.nonlinear_planes(p, ub - eps * d, rows)
+        return (a - b) / (2 * eps)
+
+    ref = lin(1e-2)
+    got = lin(1e-8)
+    assert float((got - ref).abs().max()) < 1e-13 * float(ref.abs().max())

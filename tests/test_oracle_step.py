@@ -144,11 +144,20 @@ def test_time_order_two():
 
 
 def test_next_dt_rule():
-    assert O.next_dt(1e-3, 1.0, cfl=0.5, dt_max=1e-3) == 1e-3
-    assert O.next_dt(1e-3, 1e-3, cfl=0.5, dt_max=1e-3) == 5e-4      # shrink: accept
-    assert O.next_dt(5e-4, 1.05e-3, cfl=0.5, dt_max=1e-3) == 5e-4   # +5 %: keep
-    assert O.next_dt(5e-4, 1.2e-3, cfl=0.5, dt_max=1e-3) == 6e-4    # +20 %: accept
+    assert O.next_dt(1e-3, 1.0, cfl=0.5, dt_max=1e-3) == 1e-3          # capped, kept
+    assert O.next_dt(1e-3, 1e-3, cfl=0.5, dt_max=1e-3) == 0.9 * 5e-4   # shrink with margin
+    assert O.next_dt(5e-4, 1.1e-3, cfl=0.5, dt_max=1e-3) == 5e-4       # +10 %: keep
+    assert O.next_dt(5e-4, 1.3e-3, cfl=0.5, dt_max=1e-3) == 0.9 * 6.5e-4  # +30 %: grow
     assert O.next_dt(5e-4, 1.0, cfl=0.5, dt_max=1e-3) == 1e-3
+    # a slowly falling bound changes dt only once per ~20 % drop
+    dt, changes = 5e-4, 0
+    for n in range(100):
+        b = 1.2e-3 * (1 - 0.003 * n)
+        nd = O.next_dt(dt, b, cfl=0.5, dt_max=1e-3)
+        changes += nd != dt
+        dt = nd
+        assert dt <= 0.5 * b
+    assert changes <= 3
 
 
 @pytest.mark.slow
