@@ -54,14 +54,15 @@ def kernel_bytes(name, w, prec):
         return 3 * F * S + F * S
     if name == "div":
         return 3 * S + S
-    if name == "solve_pt":
+    if name == "sweep_pt":
         b = 2 * S + nops_m * w["N_r"] * fac_row
         if F == 4:
             b += 2 * S + nops_m * w["N_r"] * fac_row
         return b
     nmodes = w["M_theta"] * w["M_z"]
-    if name == "solve_vel":
-        return 3 * S + S + 3 * S + nops_v * w["N_r"] * fac_row
+    if name == "sweep_vel":
+        # right sides f - grad p0 in place (read 3S + p0, write 3S), then sweeps
+        return 3 * S + S + 3 * S + 3 * S + 3 * S + nops_v * w["N_r"] * fac_row
     if name == "influence":
         return 3 * 18 * nmodes * 16 + nops_m * 32 + nmodes * 32
     if name == "finalize":
@@ -143,6 +144,13 @@ def run_gpu(args, wname):
                       if v[1] and kernel_bytes(k, w, "mixed") else None}
                   for k, v in tim.items()}
     ctx.close()
+    # calibration copy of known size (256 MiB read + 256 MiB written) so that
+    # hardware traffic counters of a profiled run can be scaled
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     return dict(K=K, W=W, t64=t64, tmx=tmx, err=err, dt_end=(dt64, dtmx), dominant=kname,
                 avg_us=avg_s * 1e6, bytes=byt, achieved=achieved, per_kernel=per_kernel)
 

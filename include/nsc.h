@@ -87,9 +87,10 @@ int nsc_set_stream(nsc_ctx *ctx, void *hip_stream);
 int nsc_set_precision(nsc_ctx *ctx, int mode);
 
 /* Time integration (section 2.1, predictor--corrector with variable step).
- * dt > 0 the (initial) step; dynamic = 1 enables CFL control: after each
- * nsc_step the next step is min(dt_max, cfl * dt_cfl(u^n)), accepted if it
- * shrinks the step or grows it by more than 10 %; n_corr >= 0 corrector
+ * dt > 0 the (initial) step; dynamic = 1 enables CFL control: with the
+ * bound b = cfl * dt_cfl(u^n) evaluated during step n, the next step is
+ * 0.9 b if b < dt, min(dt_max, 0.9 b) if min(dt_max, b) > 1.2 dt, else dt
+ * (the radial operators are refactorised only on such changes); n_corr >= 0 corrector
  * stages; c_implicit in (0,1] the implicit weight of the viscous term
  * (0.5 = Crank--Nicolson type).  Defaults: dt = 1e-3, dynamic = 0, cfl = 0.5,
  * dt_max = 1e-3, n_corr = 1, c = 0.5.  Radial factors are rebuilt lazily
@@ -175,8 +176,8 @@ int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
 /* Per-kernel device time accumulated since the last call, in ms (HOST array
  * of n doubles), one entry per kernel: [0] z-inverse (curl + inverse z FFT),
  * [1] theta FFTs + products, [2] forward z FFT, [3] CFL reduction,
- * [4] right sides, [5] divergence, [6] pressure/temperature sweeps,
- * [7] velocity sweeps, [8] influence coefficients, [9] finalisation,
+ * [4] right sides, [5] Poisson right side, [6] pressure/temperature sweeps,
+ * [7] velocity right sides and sweeps, [8] influence coefficients, [9] finalisation,
  * [10] factorisation; entries [11..21] the launch counts of the same
  * kernels.  Counters are reset by the call.  Timing is enabled by
  * nsc_set_profiling(ctx, 1): each kernel is then bracketed by HIP events on

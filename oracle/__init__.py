@@ -21,7 +21,7 @@ provides an independent gradient for the adjoint tests.
 from .tc import (  # noqa: F401
     Params, radial_grid, fornberg, fd_matrices, cc_weights, to_physical,
     to_spectral, herm, derived_fields, nonlinear, nonlinear_planes,
-    nonlinear_planes_direct, base_profiles,
+    nonlinear_planes_direct,
     l_operator, radial_solve, radial_solve_modes, step, next_dt, run,
     energy, base_state, initial_state, cfl_dt, weighted_norm,
 )

@@ -247,20 +247,6 @@ def _spacings(p, r):
     return dr
 
 
-def base_profiles(p, r, D1):
-    """Radial profiles of the basic state: V = A r + B/r (Couette), its
-    discrete axial vorticity Om = D1 V + V/r, and the discrete radial
-    gradient G = D1 T_b of the conduction profile (zero if isothermal)."""
-    V = p.A * r + p.B / r
-    Om = D1 @ V + V / r
-    if p.heated:
-        Tb = 0.5 + torch.log(r / p.r_i) / math.log(p.eta)
-        G = D1 @ Tb
-    else:
-        G = torch.zeros_like(r)
-    return V, Om, G
-
-
 def nonlinear_planes_direct(p, u, rows, D1=None, r=None):
     """Plain definition of the nonlinear term at the radial rows ``rows``:
     transform u, omega and grad T of the full state, form u x omega and
@@ -285,15 +271,17 @@ def nonlinear_planes_direct(p, u, rows, D1=None, r=None):
 
 def nonlinear_planes(p, u, rows, D1=None, r=None):
     """Nonlinear term at the radial rows ``rows``, evaluated with the exact
-    split u = U_b + u' about the basic state (Couette flow, conduction
-    profile), which depends on r only:
-      u x omega = U_b x Omega_b + U_b x omega' + u' x Omega_b + u' x omega',
-      -u . grad T = -U_b . grad T' - u' . grad T_b - u' . grad T'.
-    Products with the r-only basic state multiply every Fourier coefficient
-    by a radial profile (no new modes, nothing to dealias); only the
-    perturbation products go through the padded grid.  Equal to
-    nonlinear_planes_direct in exact arithmetic; the rounding errors scale
-    with the perturbation instead of the basic state.
+    split of the state into its mean (mode (0,0): a function of r only,
+    taken as the real part that the physical field carries) and the rest:
+    with mean velocity (U, V, W)(r), mean vorticity (0, -D1 W, D1 V + V/r),
+    mean temperature gradient (D1 T_m, 0, 0) and the primed remainder,
+      u x omega  = mean x mean + mean x omega' + u' x mean-vorticity + u' x omega',
+      -u . grad T = -(mean . grad T_m) - mean . grad T' - u' . grad T_m - u' . grad T'.
+    Products with r-only fields multiply every Fourier coefficient by a
+    radial profile (no new modes, nothing to dealias); only u' x omega' and
+    u' . grad T' go through the padded grid.  Equal to the plain definition
+    (nonlinear_planes_direct) in exact arithmetic, with rounding errors that
+    scale with the non-mean part of the flow.
 
     Returns (Nhat [F][len(rows)][M_theta][M_z], dt_cfl over those rows)."""
     if r is None:
@@ -301,7 +289,9 @@ def nonlinear_planes(p, u, rows, D1=None, r=None):
     if D1 is None:
         D1, _ = fd_matrices(p, r)
     rows = torch.as_tensor(rows)
-    up = u - base_state(p, r)
+    mean = u[:, :, 0, p.K].real  # [F][N_r]
+    up = u.clone()
+    up[:, :, 0, p.K] = 0.0
     spec = derived_fields(p, up, D1, r, rows)
     phys = to_physical(p, spec)  # [n][R][N_theta][N_z]
     ur, ut, uz, wr, wt, wz = phys[:6]
@@ -310,21 +300,31 @@ def nonlinear_planes(p, u, rows, D1=None, r=None):
         gr, gt, gz = phys[6:9]
         outs.append(-(ur * gr + ut * gt + uz * gz))
     Nhat = to_spectral(p, torch.stack(outs))
-    V, Om, G = base_profiles(p, r, D1)
-    Vr = V[rows][:, None, None].to(C128)
-    Omr = Om[rows][:, None, None].to(C128)
-    Nhat[0] = Nhat[0] + Vr * spec[5] + Omr * spec[1]
-    Nhat[1] = Nhat[1] - Omr * spec[0]
-    Nhat[2] = Nhat[2] - Vr * spec[3]
-    Nhat[0, :, 0, p.K] = Nhat[0, :, 0, p.K] + (V * Om)[rows]
+    # mean profiles at the rows (R-vectors) and their discrete derivatives
+    Ur, V, W = mean[0], mean[1], mean[2]
+    Om_t = -(D1 @ W)
+    Om_z = D1 @ V + V / r
+    col = lambda x: x[rows][:, None, None].to(C128)  # noqa: E731
+    cUr, cV, cW, cOt, cOz = col(Ur), col(V), col(W), col(Om_t), col(Om_z)
+    pr, pt, pz, qr, qt, qz = spec[:6]  # u' and omega' spectra
+    Nhat[0] = Nhat[0] + cV * qz - cW * qt + pt * cOz - pz * cOt
+    Nhat[1] = Nhat[1] + cW * qr - cUr * qz - pr * cOz
+    Nhat[2] = Nhat[2] + cUr * qt - cV * qr + pr * cOt
+    Nhat[0, :, 0, p.K] = Nhat[0, :, 0, p.K] + (V * Om_z - W * Om_t)[rows]
+    Nhat[1, :, 0, p.K] = Nhat[1, :, 0, p.K] - (Ur * Om_z)[rows]
+    Nhat[2, :, 0, p.K] = Nhat[2, :, 0, p.K] + (Ur * Om_t)[rows]
     if p.heated:
-        m, _ = _modes(p)
-        imr = 1j * m[None, :, None] / r[rows][:, None, None]
-        Nhat[3] = Nhat[3] - Vr * imr * up[3][rows] - G[rows][:, None, None].to(C128) * spec[0]
+        G = D1 @ mean[3]
+        cG = col(G)
+        g1, g2, g3 = spec[6:9]  # grad T' spectra
+        Nhat[3] = Nhat[3] - (cUr * g1 + cV * g2 + cW * g3 + pr * cG)
+        Nhat[3, :, 0, p.K] = Nhat[3, :, 0, p.K] - (Ur * G)[rows]
         Nhat[2] = Nhat[2] + p.Gr * u[3][rows]
     # CFL time-step bound on the padded grid, from the full velocity
     rr = r[rows][:, None, None]
+    ur = ur + Ur[rows][:, None, None]
     ut = ut + V[rows][:, None, None]
+    uz = uz + W[rows][:, None, None]
     dr = _spacings(p, r)[rows][:, None, None]
     dth = 2.0 * math.pi / p.N_theta
     dz = p.L_z / p.N_z

@@ -125,11 +125,39 @@ struct Dft<T, 8, INV> {
   }
 };
 
+// XCD-aware workgroup order: the dispatcher hands consecutive workgroups to
+// the 8 XCDs in turn, each with its own L2.  Remapping the linear workgroup
+// id gives every XCD a contiguous range of logical tiles, so neighbouring
+// tiles (which share cache lines of the transposed intermediates) meet in
+// the same L2.
+__device__ __forceinline__ int xcd_remap(int w, int G) {
+  const int q = G / 8, r = G % 8;
+  const int x = w % 8, l = w / 8;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Logical (x, y, z) block coordinates after the XCD remap.
+__device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int G = gx * gy * gridDim.z;
+  const int w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int L = xcd_remap(w, G);
+  bx = L % gx;
+  by = (L / gx) % gy;
+  bz = L / (gx * gy);
+}
+
+// Copy the n twiddles of a plan into LDS (caller synchronises).
+template <typename T>
+__device__ __forceinline__ void load_twiddles(C2<T> *dst, const C2<T> *__restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // One Stockham stage over `nlines` lines (stride ls) of length n.
 // Requires nlines * n / R <= MAXB * blockDim.x.
 template <typename T, int R, bool INV, int MAXB>
 __device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
-                                          int ns, const C2<T> *__restrict__ tw) {
+                                          int ns, const C2<T> *tw) {
   const int nb = n / R;
   const int total = nlines * nb;
   const int step = n / (ns * R);
@@ -171,12 +199,12 @@ __device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
 }
 
 // Full transform of `nlines` LDS lines; forward (e^{-}) or inverse (e^{+}),
-// unnormalised.  tw: n twiddles e^{-2 pi i t / n} in global memory.  Lines
+// unnormalised.  tw: n twiddles e^{-2 pi i t / n} (in LDS).  Lines
 // are transformed in groups small enough that every stage's butterflies fit
 // MAXB per thread (the host guarantees n / min_radix <= MAXB * blockDim.x).
 template <typename T, bool INV, int MAXB>
 __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
-                          const C2<T> *__restrict__ tw) {
+                          const C2<T> *tw) {
   const int n = plan.n;
   int gl = (MAXB * (int)blockDim.x * plan.min_radix) / n;
   if (gl < 1) gl = 1;

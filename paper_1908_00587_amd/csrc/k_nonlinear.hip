@@ -22,15 +22,18 @@
 namespace nsc {
 namespace {
 
-constexpr int kMaxB = 4;
+constexpr int kMaxB = 1;  // one butterfly per thread per stage: low register use, high occupancy
 
-// Field `f` of the derived set at (row j, mode m, kk) from the spectral state:
-// 0..2 u_r, u_theta, u_z; 3..5 omega_r, omega_theta, omega_z; 6..8 grad T.
+// Field `f` of the derived set at (row j, mode m, kk): 0..2 u_r, u_theta,
+// u_z; 3..5 omega_r, omega_theta, omega_z; 6..8 grad T.  With drop_mean the
+// mode (0,0) -- the r-only mean flow, whose products are formed exactly per
+// mode in k_zfwd -- is left out of the transforms.
 __device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
                                            const double2 *__restrict__ u, int f,
-                                           int j, int m, int kk) {
+                                           int j, int m, int kk, bool drop_mean) {
   const size_t plane = (size_t)d.nmodes;
   const size_t md = (size_t)m * d.mz + kk;
+  if (drop_mean && m == 0 && kk == d.kmax) return make_double2(0.0, 0.0);
   auto U = [&](int fld, int row) -> double2 {
     return u[((size_t)fld * d.nr + row) * plane + md];
   };
@@ -80,15 +83,17 @@ __device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
 
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
-                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm) {
+                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm, int drop_mean) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nz;
+  int bx, j, f;
+  xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax;
   const int ls = nz + 1;
-  const int mt0 = blockIdx.x * tm;
-  const int j = blockIdx.y;
-  const int f = blockIdx.z;
+  const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
+  load_twiddles(tws, tw, nz);
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int li = idx / nz;
     const int b = idx - li * nz;
@@ -97,13 +102,13 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
     if (b <= K) k = b;
     else if (b >= nz - K) k = b - nz;
     if (k != INT_MIN) {
-      double2 v = derived(d, g, u, f, j, mt0 + li, k + K);
+      double2 v = derived(d, g, u, f, j, mt0 + li, k + K, drop_mean != 0);
       val = {T(v.x), T(v.y)};
     }
     buf[li * ls + b] = val;
   }
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tw);
+  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = Z + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -119,14 +124,16 @@ template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
                         C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
                         double dth, double dzs, double *__restrict__ cfl_part,
-                        int want_cfl) {
+                        int want_cfl, const double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nt;
   __shared__ double red[kFftThreads / 64];
   const int nt = d.nt, mt = d.mt;
   const int ls = nt + 1;
-  const int b = blockIdx.x;  // z index
-  const int j = blockIdx.y;  // radial row
+  int b, j, unused;
+  xcd_block(b, j, unused);  // b: z index, j: radial row
+  load_twiddles(tws, tw, nt);
   const int npi = (n_in + 1) / 2;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   const C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
@@ -153,9 +160,10 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
     buf[p * ls + a] = v;
   }
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, npi, ls, pt, tw);
+  fft_lines<T, true, kMaxB>(buf, npi, ls, pt, tws);
   // pointwise products and CFL bound
   const double rj = g.r[j], drj = g.dr[j];
+  const double mur = mean[j], mut = mean[d.nr + j], muz = mean[2 * d.nr + j];
   double lmin = DBL_MAX;
   bool bad = false;
   const bool heated = n_in > 6;
@@ -173,7 +181,8 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
     buf[a] = {nr_, nth};
     buf[ls + a] = {nzz, ntt};
     if (want_cfl) {
-      const double aur = fabs((double)ur), aut = fabs((double)ut), auz = fabs((double)uz);
+      const double aur = fabs((double)ur + mur), aut = fabs((double)ut + mut),
+                   auz = fabs((double)uz + muz);
       if (!(isfinite(aur) && isfinite(aut) && isfinite(auz))) bad = true;
       if (aur > 0.0) lmin = fmin(lmin, drj / aur);
       if (aut > 0.0) lmin = fmin(lmin, rj * dth / aut);
@@ -181,7 +190,7 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
     }
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, 2, ls, pt, tw);
+  fft_lines<T, false, kMaxB>(buf, 2, ls, pt, tws);
   // unpack the two real transforms of each line, keep m < M_theta
   const int nout = heated ? 4 : 3;
   C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
@@ -210,23 +219,95 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
       double v = red[0];
       for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
         v = (isnan(v) || isnan(red[w])) ? NAN : fmin(v, red[w]);
-      cfl_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v;
+      cfl_part[(size_t)j * gridDim.x + b] = v;
     }
   }
 }
 
+// Terms of output field f at (j, m, kk) that involve the mean flow (mode
+// (0,0), r only): mean x mean, mean x omega', u' x mean vorticity,
+// -mean . grad T', -u' . grad T_mean, formed exactly per mode; plus the
+// buoyancy Gr T.  mean[.][j]: U_r, V, W, T_m, Om_theta = -D1 W,
+// Om_z = D1 V + V/r, G = D1 T_m.
+__device__ __forceinline__ double2 mean_terms(const Dims &d, const Grid &g,
+                                              const double2 *__restrict__ u,
+                                              const double *__restrict__ mean, int f, int j,
+                                              int m, int kk) {
+  const int n = d.nr;
+  const double Ur = mean[j], V = mean[n + j], W = mean[2 * n + j];
+  const double Ot = mean[4 * n + j], Oz = mean[5 * n + j];
+  const bool b00 = (m == 0 && kk == d.kmax);
+  auto D = [&](int fld) { return derived(d, g, u, fld, j, m, kk, true); };
+  auto lin = [](double a, double2 x, double b, double2 y) {
+    return make_double2(a * x.x + b * y.x, a * x.y + b * y.y);
+  };
+  double2 o = make_double2(0.0, 0.0);
+  if (f == 0) {
+    const double2 a = lin(V, D(5), -W, D(4)), b = lin(Oz, D(1), -Ot, D(2));
+    o = make_double2(a.x + b.x, a.y + b.y);
+    if (b00) o.x += V * Oz - W * Ot;
+  } else if (f == 1) {
+    const double2 a = lin(W, D(3), -Ur, D(5)), b = D(0);
+    o = make_double2(a.x - Oz * b.x, a.y - Oz * b.y);
+    if (b00) o.x -= Ur * Oz;
+  } else if (f == 2) {
+    const double2 a = lin(Ur, D(4), -V, D(3)), b = D(0);
+    o = make_double2(a.x + Ot * b.x, a.y + Ot * b.y);
+    if (b00) o.x += Ur * Ot;
+    if (d.heated) {
+      const double2 t = u[((size_t)3 * n + j) * d.nmodes + (size_t)m * d.mz + kk];
+      o.x += d.gr * t.x;
+      o.y += d.gr * t.y;
+    }
+  } else {
+    const double G = mean[6 * n + j];
+    const double2 a = lin(Ur, D(6), V, D(7)), b = lin(W, D(8), G, D(0));
+    o = make_double2(-(a.x + b.x), -(a.y + b.y));
+    if (b00) o.x -= Ur * G;
+  }
+  return o;
+}
+
+// Mean-flow profiles of mode (0,0) per radial row (real parts, as carried
+// by the physical field) and their discrete derivatives.
+__global__ void k_mean(Dims d, Grid g, const double2 *__restrict__ u, double *__restrict__ mean) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = d.nr;
+  if (j >= n) return;
+  const size_t P = d.nmodes;
+  auto M = [&](int f, int row) { return u[((size_t)f * n + row) * P + d.kmax].x; };
+  const int s = g.s[j];
+  const double *w = g.d1 + j * kStencil;
+  double dv = 0.0, dw = 0.0, dt = 0.0;
+  for (int t = 0; t < kStencil; ++t) {
+    dv = fma(w[t], M(1, s + t), dv);
+    dw = fma(w[t], M(2, s + t), dw);
+    if (d.heated) dt = fma(w[t], M(3, s + t), dt);
+  }
+  mean[j] = M(0, j);
+  mean[n + j] = M(1, j);
+  mean[2 * n + j] = M(2, j);
+  mean[3 * n + j] = d.heated ? M(3, j) : 0.0;
+  mean[4 * n + j] = -dw;
+  mean[5 * n + j] = dv + M(1, j) * g.rinv[j];
+  mean[6 * n + j] = dt;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, FftPlan pz, const C2<T> *__restrict__ W,
+__global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz, const C2<T> *__restrict__ W,
                        const double2 *__restrict__ u, double2 *__restrict__ nh,
-                       const C2<T> *__restrict__ tw, int tm, double scale) {
+                       const C2<T> *__restrict__ tw, int tm, double scale,
+                       const double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nz;
+  int bx, j, f;
+  xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
   const int ls = nz + 1;
-  const int mt0 = blockIdx.x * tm;
-  const int j = blockIdx.y;
-  const int f = blockIdx.z;
+  const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
+  load_twiddles(tws, tw, nz);
   const C2<T> *in = W + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -234,31 +315,22 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, FftPlan pz, const 
     buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tw);
+  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
-  const bool buoy = (f == 2) && d.heated;
   for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
     const int li = idx / mz;
     const int kk = idx - li * mz;
     const int m = mt0 + li;
     const int k = kk - K;
     const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
-    double2 o = {(double)v.x * scale, (double)v.y * scale};
+    const double2 bt = mean_terms(d, g, u, mean, f, j, m, kk);
+    double2 o = {(double)v.x * scale + bt.x, (double)v.y * scale + bt.y};
     const size_t md = (size_t)m * mz + kk;
-    if (buoy) {
-      const double2 t = u[((size_t)3 * d.nr + j) * plane + md];
-      o.x += d.gr * t.x;
-      o.y += d.gr * t.y;
-    }
     if (m == 0) {
       const int kkm = mz - 1 - kk;
       const C2<T> vm = buf[li * ls + (k <= 0 ? -k : nz - k)];
-      double2 om = {(double)vm.x * scale, (double)vm.y * scale};
-      if (buoy) {
-        const double2 t = u[((size_t)3 * d.nr + j) * plane + kkm];
-        om.x += d.gr * t.x;
-        om.y += d.gr * t.y;
-      }
+      const double2 bm = mean_terms(d, g, u, mean, f, j, m, kkm);
+      const double2 om = {(double)vm.x * scale + bm.x, (double)vm.y * scale + bm.y};
       o = {0.5 * (o.x + om.x), 0.5 * (o.y - om.y)};
     }
     nh[((size_t)f * d.nr + j) * plane + md] = o;
@@ -301,13 +373,15 @@ __global__ void __launch_bounds__(kFftThreads)
 k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict__ W,
            const C2<T> *__restrict__ tw, int tm, double scale) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nz;
+  int bx, j, f;
+  xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
   const int ls = nz + 1;
-  const int mt0 = blockIdx.x * tm;
-  const int j = blockIdx.y;
-  const int f = blockIdx.z;
+  const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
+  load_twiddles(tws, tw, nz);
   const size_t plane = (size_t)d.nmodes;
   const double2 *src = nb + ((size_t)f * d.nr + j) * plane;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
@@ -331,7 +405,7 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
     buf[li * ls + b] = val;
   }
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tw);
+  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = W + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -370,11 +444,13 @@ __global__ void __launch_bounds__(kFftThreads)
 k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
             const C2<T> *__restrict__ tw, int n_in, int n_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nt;
   const int nt = d.nt, mt = d.mt;
   const int ls = nt + 1;
-  const int b = blockIdx.x;
-  const int j = blockIdx.y;
+  int b, j, unused;
+  xcd_block(b, j, unused);
+  load_twiddles(tws, tw, nt);
   const int npi = (n_in + 1) / 2;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
@@ -382,7 +458,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
   for (int p = 0; p < npi; ++p) pack_line(buf + p * ls, zl, fstride, 2 * p, 2 * p + 1, n_in, nt, mt);
   for (int p = 0; p < 2; ++p) pack_line(buf + (npi + p) * ls, wl, fstride, 2 * p, 2 * p + 1, n_out, nt, mt);
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, npi + 2, ls, pt, tw);
+  fft_lines<T, true, kMaxB>(buf, npi + 2, ls, pt, tws);
   const bool heated = n_in > 6;
   for (int a = threadIdx.x; a < nt; a += blockDim.x) {
     const C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
@@ -408,7 +484,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
     buf[2 * ls + a] = {bwt, bwz};
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, npi, ls, pt, tw);
+  fft_lines<T, false, kMaxB>(buf, npi, ls, pt, tws);
   for (int idx = threadIdx.x; idx < npi * mt; idx += blockDim.x) {
     const int p = idx / mt;
     const int m = idx - p * mt;
@@ -427,13 +503,15 @@ __global__ void __launch_bounds__(kFftThreads)
 k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict__ db,
            const C2<T> *__restrict__ tw, int tm) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  C2<T> *buf = tws + d.nz;
+  int bx, j, f;
+  xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
   const int ls = nz + 1;
-  const int mt0 = blockIdx.x * tm;
-  const int j = blockIdx.y;
-  const int f = blockIdx.z;
+  const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
+  load_twiddles(tws, tw, nz);
   const C2<T> *in = Z + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -441,7 +519,7 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
     buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tw);
+  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
   for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
     const int li = idx / mz;
@@ -450,7 +528,8 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
     const int k = kk - K;
     const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
     const double cm = m == 0 ? 1.0 : 2.0;
-    db[((size_t)f * d.nr + j) * plane + (size_t)m * mz + kk] = make_double2(cm * (double)v.x, cm * (double)v.y);
+    double2 o = make_double2(cm * (double)v.x, cm * (double)v.y);
+    db[((size_t)f * d.nr + j) * plane + (size_t)m * mz + kk] = o;
   }
 }
 
@@ -499,11 +578,15 @@ __global__ void k_derived_adj(Dims d, Grid g, const double2 *__restrict__ db,
   add(2, make_double2(d2.x + c3.x - t4.x, d2.y + c3.y - t4.y));
   if (d.heated) {
     const double2 t6 = D1T(6), e7 = mul_i(-mr, D(7)), e8 = mul_i(-kap, D(8));
-    double2 nz = nb[((size_t)2 * n + j) * P + md];
-    if (md < d.mz) {
-      const double2 w = nb[((size_t)2 * n + j) * P + (d.mz - 1 - md)];
-      nz = make_double2(0.5 * (nz.x + w.x), 0.5 * (nz.y - w.y));
-    }
+    auto NB = [&](int fo) {
+      double2 a = nb[((size_t)fo * n + j) * P + md];
+      if (md < d.mz) {
+        const double2 w = nb[((size_t)fo * n + j) * P + (d.mz - 1 - md)];
+        a = make_double2(0.5 * (a.x + w.x), 0.5 * (a.y - w.y));
+      }
+      return a;
+    };
+    const double2 nz = NB(2);
     add(3, make_double2(t6.x + e7.x + e8.x + d.gr * nz.x, t6.y + e7.y + e8.y + d.gr * nz.y));
   }
 }
@@ -523,10 +606,10 @@ int block_for(const FftPlan &p, int nlines, int floor_threads) {
 
 // Lines per block for the z passes: LDS budget and butterfly budget.
 int z_lines(const nsc_ctx *c, size_t esize) {
-  const size_t budget = 64 * 1024;
+  const size_t budget = (size_t)c->lds_max - (size_t)c->d.nz * esize;
   int tm = (int)(budget / ((size_t)(c->d.nz + 1) * esize));
-  const int bf_cap = kMaxB * kFftThreads * min_radix(c->plan_z) / c->d.nz;
-  if (tm > bf_cap) tm = bf_cap;
+  // lines beyond one butterfly per thread are transformed in groups; the
+  // width of the transposed accesses (tm consecutive theta modes) matters more
   if (tm > 16) tm = 16;
   if (tm > c->d.mt) tm = c->d.mt;
   if (tm < 1) tm = 1;
@@ -538,11 +621,13 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const int threads = block_for(c->plan_z, tm, 256);
-  const size_t shm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
+  hipLaunchKernelGGL(k_mean, dim3((c->d.nr + 63) / 64), dim3(64), 0, c->stream, c->d, c->g,
+                     reinterpret_cast<const double2 *>(u), c->s_mean);
   hipLaunchKernelGGL(k_zinv<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
                      c->plan_z, reinterpret_cast<const double2 *>(u),
                      reinterpret_cast<C2<T> *>(c->zbuf),
-                     reinterpret_cast<const C2<T> *>(tw), tm);
+                     reinterpret_cast<const C2<T> *>(tw), tm, 1);
   return hipGetLastError();
 }
 
@@ -551,14 +636,14 @@ hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
   dim3 grid(c->d.nz, c->d.nr);
   const int npi = (c->n_in + 1) / 2;
   const int threads = block_for(c->plan_t, npi, 256);
-  const size_t shm = (size_t)npi * (c->d.nt + 1) * sizeof(C2<T>);
+  const size_t shm = ((size_t)npi * (c->d.nt + 1) + c->d.nt) * sizeof(C2<T>);
   const double dth = 2.0 * M_PI / c->d.nt;
   const double dzs = c->d.lz / c->d.nz;
   hipLaunchKernelGGL(k_theta<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
                      c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
                      reinterpret_cast<C2<T> *>(c->wbuf),
                      reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
-                     c->cfl_part, want_cfl);
+                     c->cfl_part, want_cfl, c->s_mean);
   return hipGetLastError();
 }
 
@@ -567,12 +652,12 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw)
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
   const int threads = block_for(c->plan_z, tm, 256);
-  const size_t shm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
-  hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->plan_z,
+  hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->g, c->plan_z,
                      reinterpret_cast<const C2<T> *>(c->wbuf),
                      reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
-                     reinterpret_cast<const C2<T> *>(tw), tm, scale);
+                     reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean);
   return hipGetLastError();
 }
 
@@ -582,11 +667,11 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
                               const T *twz, const T *twt) {
   const int tm = z_lines(c, sizeof(C2<T>));
   const int zthreads = block_for(c->plan_z, tm, 256);
-  const size_t zshm = (size_t)tm * (c->d.nz + 1) * sizeof(C2<T>);
+  const size_t zshm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
   // forward fields on the (r, theta-spectral, z-physical) grid
   hipLaunchKernelGGL(k_zinv<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads), zshm,
                      c->stream, c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
-                     reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz), tm);
+                     reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz), tm, 0);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
   hipLaunchKernelGGL(k_zinv_adj<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out), dim3(zthreads),
                      zshm, c->stream, c->d, c->plan_z, reinterpret_cast<const double2 *>(nbar),
@@ -594,7 +679,7 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
                      scale);
   const int npi = (c->n_in + 1) / 2;
   const int tthreads = block_for(c->plan_t, npi + 2, 256);
-  const size_t tshm = (size_t)(npi + 2) * (c->d.nt + 1) * sizeof(C2<T>);
+  const size_t tshm = ((size_t)(npi + 2) * (c->d.nt + 1) + c->d.nt) * sizeof(C2<T>);
   hipLaunchKernelGGL(k_theta_adj<T>, dim3(c->d.nz, c->d.nr), dim3(tthreads), tshm, c->stream, c->d,
                      c->plan_t, reinterpret_cast<C2<T> *>(c->zbuf),
                      reinterpret_cast<const C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twt),

@@ -152,55 +152,67 @@ k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_o
   }
 }
 
-// Forward/back substitution for one lane.  RHS(j) gives b_j, OUT(j) the
-// storage for y_j then x_j (global, read back by the same lane).
-template <typename V, typename RHS, typename OUT>
-__device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rhs, OUT out) {
+// Forward/back substitution for one lane.  RHS(j) gives b_j, COL(j) the
+// storage of y_j then x_j (LDS or global, read back by the same lane).  The
+// bulk rows carry no branches: the envelope slots outside the matrix are
+// stored as zeros, so every row issues the same independent loads and the
+// compiler can schedule them ahead of the recurrence; only the one-sided
+// wall rows (U to column 8 in rows 0..3, L from column N-9 in rows N-4..N-1)
+// take the extra edge terms, in peeled loops.
+template <typename V, typename RHS, typename COL>
+__device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rhs, COL col) {
   const size_t nops = F.nops;
-  const double *vals = F.vals + op;
-  const double *edge = F.edge + op;
-  V yb[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) yb[t] = V{};
-  for (int j = 0; j < n; ++j) {
+  const double *__restrict__ vals = F.vals + op;
+  const double *__restrict__ edge = F.edge + op;
+  V y1{}, y2{}, y3{}, y4{};
+#pragma unroll 4
+  for (int j = 0; j < n - 4; ++j) {
+    const double *v = vals + (size_t)j * kSlots * nops;
+    const double l4 = v[0], l3 = v[nops], l2 = v[2 * nops], l1 = v[3 * nops];
     V y = rhs(j);
-    const double *v = vals + (size_t)j * kSlots * nops;
-#pragma unroll
-    for (int t = 1; t <= 4; ++t)
-      if (j - t >= 0) y = y - v[(size_t)(4 - t) * nops] * yb[t - 1];
-    if (j >= n - 4) {
-      const int tt = n - 1 - j;
-#pragma unroll
-      for (int b = 5; b <= 8; ++b) {
-        const int c = j - b;
-        if (c >= n - 9 && c >= 0) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * yb[b - 1];
-      }
-    }
-#pragma unroll
-    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
-    yb[0] = y;
-    out(j) = y;
+    y = y - l1 * y1;
+    y = y - l2 * y2;
+    y = y - l3 * y3;
+    y = y - l4 * y4;
+    y4 = y3;
+    y3 = y2;
+    y2 = y1;
+    y1 = y;
+    col(j) = y;
   }
-#pragma unroll
-  for (int t = 0; t < 8; ++t) yb[t] = V{};
-  for (int j = n - 1; j >= 0; --j) {
-    V x = out(j);
+  for (int j = n - 4; j < n; ++j) {
     const double *v = vals + (size_t)j * kSlots * nops;
+    V y = rhs(j);
 #pragma unroll
-    for (int t = 1; t <= 4; ++t)
-      if (j + t < n) x = x - v[(size_t)(4 + t) * nops] * yb[t - 1];
-    if (j <= 3) {
+    for (int t = 1; t <= 4; ++t) y = y - v[(size_t)(4 - t) * nops] * col(j - t);
+    const int tt = n - 1 - j;
+    for (int c = n - 9; c <= j - 5; ++c) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * col(c);
+    col(j) = y;
+  }
+  V x1{}, x2{}, x3{}, x4{};
+#pragma unroll 4
+  for (int j = n - 1; j >= 4; --j) {
+    const double *v = vals + (size_t)j * kSlots * nops;
+    const double di = v[4 * nops], u1 = v[5 * nops], u2 = v[6 * nops], u3 = v[7 * nops], u4 = v[8 * nops];
+    V x = col(j);
+    x = x - u1 * x1;
+    x = x - u2 * x2;
+    x = x - u3 * x3;
+    x = x - u4 * x4;
+    x = di * x;
+    x4 = x3;
+    x3 = x2;
+    x2 = x1;
+    x1 = x;
+    col(j) = x;
+  }
+  for (int j = 3; j >= 0; --j) {
+    const double *v = vals + (size_t)j * kSlots * nops;
+    V x = col(j);
 #pragma unroll
-      for (int b = 5; b <= 8; ++b) {
-        const int c = j + b;
-        if (c <= 8 && c < n) x = x - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * yb[b - 1];
-      }
-    }
-    x = v[(size_t)4 * nops] * x;
-#pragma unroll
-    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
-    yb[0] = x;
-    out(j) = x;
+    for (int t = 1; t <= 4; ++t) x = x - v[(size_t)(4 + t) * nops] * col(j + t);
+    for (int c = j + 5; c <= 8; ++c) x = x - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * col(c);
+    col(j) = v[(size_t)4 * nops] * x;
   }
 }
 
@@ -364,13 +376,220 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
   }
 }
 
-// g = 1/2 [(D1 + (1+m)/r) f+ + (D1 + (1-m)/r) f-] + i kappa f_z; zero wall rows.
-__global__ void k_div(Dims d, Grid g, const double2 *__restrict__ sf, double2 *__restrict__ sg) {
+// ---------------------------------------------------------------------------
+// Batched sweeps: one lane per (mode, system), the system's right side given
+// column-wise in global memory (rows strided by the mode count).  The
+// intermediate y and the solution x stay in LDS (64 lanes x N_r complex) so
+// the two recurrences issue no global stores and the factor / right-side
+// loads of later rows can be scheduled ahead; the solution is copied out at
+// the end.  Columns longer than the LDS budget keep y in the output array.
+// ---------------------------------------------------------------------------
+struct SweepSys {
+  Factors F, F00;
+  int qmode;   // 0: q = m, 1: q = m + 1, 2: q = |m - 1|
+  int mode00;  // 0: regular operator, 1: use F00 (single op), 2: write zeros
+  const double2 *in;  // right side column base, rows strided by the mode count
+  double2 *out;       // solution column base
+};
+struct SweepArgs {
+  SweepSys s[3];
+};
+constexpr int kSweepLanes = 64;
+
+template <bool USE_LDS>
+__global__ void __launch_bounds__(kSweepLanes)
+k_sweep(Dims d, SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cd *col = reinterpret_cast<Cd *>(smem);
+  const int lane = threadIdx.x;
+  const int md = blockIdx.x * kSweepLanes + lane;
+  if (md >= d.nmodes) return;
+  const SweepSys &S = a.s[blockIdx.y];
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  const double2 *__restrict__ b = S.in + md;
+  double2 *__restrict__ x = S.out + md;
+  Factors F = S.F;
+  const int q = S.qmode == 0 ? m : (S.qmode == 1 ? m + 1 : (m >= 1 ? m - 1 : 1 - m));
+  int op = q * kp1 + ka;
+  if (m == 0 && ka == 0) {
+    if (S.mode00 == 2) {
+      for (int j = 0; j < n; ++j) x[(size_t)j * P] = make_double2(0.0, 0.0);
+      return;
+    }
+    if (S.mode00 == 1) {
+      F = S.F00;
+      op = 0;
+    }
+  }
+  if (!USE_LDS) {
+    lu_solve<Cd>(F, op, n, [&](int j) { return ld(b + (size_t)j * P); },
+                 [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(x + (size_t)j * P); });
+    return;
+  }
+  const size_t nops = F.nops;
+  const double *__restrict__ vals = F.vals + op;
+  const double *__restrict__ edge = F.edge + op;
+  auto C = [&](int j) -> Cd & { return col[j * kSweepLanes + lane]; };
+  // right side into the LDS column with all loads in flight together
+#pragma unroll 8
+  for (int j = 0; j < n; ++j) C(j) = ld(b + (size_t)j * P);
+  // forward substitution over the bulk rows, factor rows prefetched 4 ahead
+  const int nm = n - 4;
+  auto row = [&](int j, int sl) { return vals[((size_t)j * kSlots + sl) * nops]; };
+  double fa[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jj = r < nm ? r : nm - 1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
+  }
+  Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
+  for (int j0 = 0; j0 < nm; j0 += 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + r;
+      if (j < nm) {
+        Cd y = C(j);
+        y = y - fa[r][3] * y1;
+        y = y - fa[r][2] * y2;
+        y = y - fa[r][1] * y3;
+        y = y - fa[r][0] * y4;
+        y4 = y3;
+        y3 = y2;
+        y2 = y1;
+        y1 = y;
+        C(j) = y;
+      }
+      const int jn = j + 4 < nm ? j + 4 : nm - 1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
+    }
+  }
+  for (int j = nm; j < n; ++j) {
+    Cd y = C(j);
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) y = y - row(j, 4 - t) * C(j - t);
+    const int tt = n - 1 - j;
+    for (int c = n - 9; c <= j - 5; ++c) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * C(c);
+    C(j) = y;
+  }
+  // back substitution over rows N-1..4, prefetched 4 ahead
+  double u[4][5];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jj = n - 1 - r >= 4 ? n - 1 - r : 4;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
+  }
+  Cd x1{0, 0}, x2{0, 0}, x3{0, 0}, x4{0, 0};
+  for (int j0 = n - 1; j0 >= 4; j0 -= 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 - r;
+      if (j >= 4) {
+        Cd xv = C(j);
+        xv = xv - u[r][1] * x1;
+        xv = xv - u[r][2] * x2;
+        xv = xv - u[r][3] * x3;
+        xv = xv - u[r][4] * x4;
+        xv = u[r][0] * xv;
+        x4 = x3;
+        x3 = x2;
+        x2 = x1;
+        x1 = xv;
+        C(j) = xv;
+      }
+      const int jn = j - 4 >= 4 ? j - 4 : 4;
+#pragma unroll
+      for (int t = 0; t < 5; ++t) u[r][t] = row(jn, 4 + t);
+    }
+  }
+  for (int j = 3; j >= 0; --j) {
+    Cd xv = C(j);
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) xv = xv - row(j, 4 + t) * C(j + t);
+    for (int c = j + 5; c <= 8; ++c) xv = xv - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * C(c);
+    C(j) = row(j, 4) * xv;
+  }
+#pragma unroll 8
+  for (int j = 0; j < n; ++j) st(x + (size_t)j * P, C(j));
+}
+
+
+// Velocity right sides in place of f: f_X - (grad p0)_X inside, wall values
+// on rows 0 and N-1; mode (0,0) solves u_theta directly (X+- = +-i u_theta).
+__global__ void k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ sp,
+                          int walls) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const bool zero = (md == d.kmax);
+  double2 *fp = sf + (size_t)j * P + md, *fm = sf + ((size_t)n + j) * P + md,
+          *fz = sf + ((size_t)2 * n + j) * P + md;
+  if (j == 0 || j == n - 1) {
+    Cd wp = {0, 0};
+    if (zero && walls) {
+      const double re = j == 0 ? d.re_i : d.re_o;
+      wp = {0.0, re};
+    }
+    st(fp, wp);
+    st(fm, Cd{-wp.x, -wp.y});
+    st(fz, Cd{0, 0});
+    return;
+  }
+  if (zero) {
+    const Cd h = 0.5 * (ld(fp) - ld(fm));
+    st(fp, h);
+    st(fm, Cd{-h.x, -h.y});
+    return;
+  }
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const double2 *p = sp + md;
+  const Cd pj = ld(p + (size_t)j * P);
+  const Cd dp = d1_rowc(g, j, p, P);
+  const Cd mp = (m * g.rinv[j]) * pj;
+  st(fp, ld(fp) - (dp - mp));
+  st(fm, ld(fm) - (dp + mp));
+  st(fz, ld(fz) - kap * ci(pj));
+}
+
+// Poisson right side g = mask(div f); for mode (0,0) the mean-head right side
+// (D1 + 1/r) F_r inside, F_r(r_o) at the outer wall (zeros if not requested).
+__global__ void k_div2(Dims d, Grid g, const double2 *__restrict__ sf, double2 *__restrict__ sg,
+                       const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc,
+                       int want_p) {
+  const int md = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  if (md == d.kmax) {
+    Cd r = {0, 0};
+    if (want_p && nn && j > 0) {
+      auto Fr = [&](int t) {
+        return cc * ld(nq + (size_t)t * P + md) + (1.0 - cc) * ld(nn + (size_t)t * P + md);
+      };
+      if (j == n - 1) {
+        r = Fr(n - 1);
+      } else {
+        const int s0 = g.s[j];
+        const double *w = g.d1 + j * kStencil;
+        r = g.rinv[j] * Fr(j);
+        for (int t = 0; t < kStencil; ++t) r = fmac(w[t], Fr(s0 + t), r);
+      }
+    }
+    st(sg + (size_t)j * P + md, r);
+    return;
+  }
   if (j == 0 || j == n - 1) {
     st(sg + (size_t)j * P + md, Cd{0, 0});
     return;
@@ -382,112 +601,18 @@ __global__ void k_div(Dims d, Grid g, const double2 *__restrict__ sf, double2 *_
   const double2 *fp = sf + md, *fm = sf + (size_t)n * P + md, *fz = sf + (size_t)2 * n * P + md;
   const Cd dp = d1_rowc(g, j, fp, P), dm = d1_rowc(g, j, fm, P);
   const Cd vp = ld(fp + (size_t)j * P), vm = ld(fm + (size_t)j * P), vz = ld(fz + (size_t)j * P);
-  const Cd gval = 0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz);
-  st(sg + (size_t)j * P + md, gval);
+  st(sg + (size_t)j * P + md,
+     0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz));
 }
 
-// sys 0: pressure p0 (mode (0,0): mean head if requested); sys 1: temperature.
-__global__ void __launch_bounds__(256) k_solve_pt(Dims d, Grid g, Factors fp, Factors fp00, Factors ft,
-                           const double2 *__restrict__ sg, const double2 *__restrict__ sf,
-                           const double2 *__restrict__ nn, const double2 *__restrict__ nq,
-                           double2 *__restrict__ sp, double2 *__restrict__ sT, double cc,
-                           int walls, int want_p) {
+// Temperature wall rows of f_T replaced by the wall values (+-1/2 in (0,0)).
+__global__ void k_t_walls(Dims d, double2 *__restrict__ sfT, int walls) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
-  const int sys = blockIdx.y;
   const size_t P = d.nmodes;
-  const int n = d.nr;
-  const int kp1 = d.kmax + 1;
-  const int m = md / d.mz;
-  const int kk = md - m * d.mz;
-  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
-  const bool zero = (m == 0 && ka == 0);
-  auto out_p = [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(sp + (size_t)j * P + md); };
-  if (sys == 0) {
-    if (zero) {
-      if (want_p && nn) {
-        // dp/dr = F_r in divergence form: rhs (D1 + 1/r) F_r, F_r(r_o) at the wall
-        auto Fr = [&](int t) {
-          return cc * ld(nq + (size_t)t * P + md) + (1.0 - cc) * ld(nn + (size_t)t * P + md);
-        };
-        lu_solve<Cd>(fp00, 0, n,
-                     [&](int j) {
-                       if (j == 0) return Cd{0, 0};
-                       if (j == n - 1) return Fr(n - 1);
-                       const int s0 = g.s[j];
-                       const double *w = g.d1 + j * kStencil;
-                       Cd acc = g.rinv[j] * Fr(j);
-                       for (int t = 0; t < kStencil; ++t) acc = fmac(w[t], Fr(s0 + t), acc);
-                       return acc;
-                     },
-                     out_p);
-      } else {
-        for (int j = 0; j < n; ++j) out_p(j) = Cd{0, 0};
-      }
-      return;
-    }
-    lu_solve<Cd>(fp, m * kp1 + ka, n, [&](int j) { return ld(sg + (size_t)j * P + md); }, out_p);
-  } else {
-    const double2 *fT = sf + (size_t)3 * n * P + md;
-    const Cd w0 = (zero && walls) ? Cd{0.5, 0} : Cd{0, 0};
-    const Cd w1 = (zero && walls) ? Cd{-0.5, 0} : Cd{0, 0};
-    lu_solve<Cd>(ft, m * kp1 + ka, n,
-                 [&](int j) {
-                   if (j == 0) return w0;
-                   if (j == n - 1) return w1;
-                   return ld(fT + (size_t)j * P);
-                 },
-                 [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(sT + (size_t)j * P + md); });
-  }
-}
-
-// comp 0: X0+, 1: X0-, 2: X0z.
-__global__ void __launch_bounds__(256) k_solve_vel(Dims d, Grid g, Factors fv, const double2 *__restrict__ sf,
-                            const double2 *__restrict__ sp, double2 *__restrict__ sx, int walls) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  if (md >= d.nmodes) return;
-  const int comp = blockIdx.y;
-  const size_t P = d.nmodes;
-  const int n = d.nr;
-  const int kp1 = d.kmax + 1;
-  const int m = md / d.mz;
-  const int kk = md - m * d.mz;
-  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
-  const double kap = (double)(kk - d.kmax) * d.kz;
-  const bool zero = (m == 0 && ka == 0);
-  const int q = comp == 0 ? m + 1 : (comp == 1 ? (m >= 1 ? m - 1 : 1 - m) : m);
-  const double2 *f = sf + (size_t)comp * n * P + md;
-  const double2 *fp = sf + md, *fm = sf + (size_t)n * P + md;
-  const double2 *p = sp + md;
-  double2 *out = sx + (size_t)comp * n * P + md;
-  const double mm = (double)m;
-  Cd w0 = {0, 0}, w1 = {0, 0};
-  if (zero && walls && comp < 2) {
-    const double sgn = comp == 0 ? 1.0 : -1.0;  // X+- = +-i u_theta
-    w0 = {0.0, sgn * d.re_i};
-    w1 = {0.0, sgn * d.re_o};
-  }
-  auto rhs = [&](int j) -> Cd {
-    if (j == 0) return w0;
-    if (j == n - 1) return w1;
-    if (zero) {
-      if (comp == 2) return ld(f + (size_t)j * P);
-      const Cd h = 0.5 * (ld(fp + (size_t)j * P) - ld(fm + (size_t)j * P));
-      return comp == 0 ? h : Cd{-h.x, -h.y};
-    }
-    const Cd pj = ld(p + (size_t)j * P);
-    Cd gp;
-    if (comp == 2) {
-      gp = kap * ci(pj);
-    } else {
-      const Cd dp = d1_rowc(g, j, p, P);
-      const double mr = mm * g.rinv[j];
-      gp = comp == 0 ? dp - mr * pj : dp + mr * pj;
-    }
-    return ld(f + (size_t)j * P) - gp;
-  };
-  lu_solve<Cd>(fv, q * kp1 + ka, n, rhs,
-               [&](int j) -> Cd & { return *reinterpret_cast<Cd *>(out + (size_t)j * P); });
+  const bool zero = (md == d.kmax) && walls;
+  st(sfT + md, Cd{zero ? 0.5 : 0.0, 0.0});
+  st(sfT + (size_t)(d.nr - 1) * P + md, Cd{zero ? -0.5 : 0.0, 0.0});
 }
 
 // lambda = -A^-1 beta(X0), beta = divergence at the two walls.
@@ -681,56 +806,61 @@ __global__ void k_add_base(Dims d, Grid g, const double2 *__restrict__ pert, dou
 // are conjugate-transposed (real factors transpose, i -> -i).
 // ---------------------------------------------------------------------------
 
-// A^T x = b with A = L U in envelope storage: U^T y = b, then L^T x = y.
-template <typename V, typename RHS, typename OUT>
-__device__ __forceinline__ void lu_solve_t(const Factors &F, int op, int n, RHS rhs, OUT out) {
+// A^T x = b with A = L U in envelope storage: U^T y = b (forward), then
+// L^T x = y (backward).  Rows 0..8 of the forward pass and N-9..N-1 of the
+// backward pass carry the one-sided edge entries and are peeled.
+template <typename V, typename RHS, typename COL>
+__device__ __forceinline__ void lu_solve_t(const Factors &F, int op, int n, RHS rhs, COL col) {
   const size_t nops = F.nops;
-  const double *vals = F.vals + op;
-  const double *edge = F.edge + op;
-  V yb[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) yb[t] = V{};
-  for (int j = 0; j < n; ++j) {
+  const double *__restrict__ vals = F.vals + op;
+  const double *__restrict__ edge = F.edge + op;
+  auto Vv = [&](int row, int slot) { return vals[((size_t)row * kSlots + slot) * nops]; };
+  for (int j = 0; j < 9; ++j) {
     V y = rhs(j);
-#pragma unroll
-    for (int t = 1; t <= 4; ++t) {
-      const int c = j - t;
-      if (c >= 0) y = y - vals[((size_t)c * kSlots + 4 + t) * nops] * yb[t - 1];
-    }
-    if (j <= 8) {
-#pragma unroll
-      for (int b = 5; b <= 8; ++b) {
-        const int c = j - b;
-        if (c >= 0 && c <= 3) y = y - edge[(size_t)(edge_off(c) + j - c - 5) * nops] * yb[b - 1];
-      }
-    }
-    y = vals[((size_t)j * kSlots + 4) * nops] * y;
-#pragma unroll
-    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
-    yb[0] = y;
-    out(j) = y;
+    for (int t = 1; t <= 4; ++t)
+      if (j - t >= 0) y = y - Vv(j - t, 4 + t) * col(j - t);
+    for (int c = 0; c <= 3; ++c)
+      if (j - c >= 5) y = y - edge[(size_t)(edge_off(c) + j - c - 5) * nops] * col(c);
+    col(j) = Vv(j, 4) * y;
   }
-#pragma unroll
-  for (int t = 0; t < 8; ++t) yb[t] = V{};
-  for (int j = n - 1; j >= 0; --j) {
-    V x = out(j);
-#pragma unroll
-    for (int t = 1; t <= 4; ++t) {
-      const int c = j + t;
-      if (c < n) x = x - vals[((size_t)c * kSlots + 4 - t) * nops] * yb[t - 1];
-    }
-    if (j >= n - 9) {
-#pragma unroll
-      for (int b = 5; b <= 8; ++b) {
-        const int c = j + b;
-        if (c <= n - 1 && c >= n - 4)
-          x = x - edge[(size_t)(10 + edge_off(n - 1 - c) + j - (n - 9)) * nops] * yb[b - 1];
-      }
-    }
-#pragma unroll
-    for (int t = 7; t > 0; --t) yb[t] = yb[t - 1];
-    yb[0] = x;
-    out(j) = x;
+  V y1 = col(8), y2 = col(7), y3 = col(6), y4 = col(5);
+#pragma unroll 4
+  for (int j = 9; j < n; ++j) {
+    const double a1 = Vv(j - 1, 5), a2 = Vv(j - 2, 6), a3 = Vv(j - 3, 7), a4 = Vv(j - 4, 8), di = Vv(j, 4);
+    V y = rhs(j);
+    y = y - a1 * y1;
+    y = y - a2 * y2;
+    y = y - a3 * y3;
+    y = y - a4 * y4;
+    y = di * y;
+    y4 = y3;
+    y3 = y2;
+    y2 = y1;
+    y1 = y;
+    col(j) = y;
+  }
+  for (int j = n - 1; j >= n - 9; --j) {
+    V x = col(j);
+    for (int t = 1; t <= 4; ++t)
+      if (j + t < n) x = x - Vv(j + t, 4 - t) * col(j + t);
+    for (int c = n - 4; c <= n - 1; ++c)
+      if (c - j >= 5) x = x - edge[(size_t)(10 + edge_off(n - 1 - c) + j - (n - 9)) * nops] * col(c);
+    col(j) = x;
+  }
+  V x1 = col(n - 9), x2 = col(n - 8), x3 = col(n - 7), x4 = col(n - 6);
+#pragma unroll 4
+  for (int j = n - 10; j >= 0; --j) {
+    const double a1 = Vv(j + 1, 3), a2 = Vv(j + 2, 2), a3 = Vv(j + 3, 1), a4 = Vv(j + 4, 0);
+    V x = col(j);
+    x = x - a1 * x1;
+    x = x - a2 * x2;
+    x = x - a3 * x3;
+    x = x - a4 * x4;
+    x4 = x3;
+    x3 = x2;
+    x2 = x1;
+    x1 = x;
+    col(j) = x;
   }
 }
 
@@ -1054,30 +1184,6 @@ hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const
   return hipGetLastError();
 }
 
-hipError_t launch_div(const nsc_ctx *c) {
-  hipLaunchKernelGGL(k_div, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
-                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<double2 *>(c->s_g));
-  return hipGetLastError();
-}
-
-hipError_t launch_solve_pt(const nsc_ctx *c, const double *nn, const double *nq, double cc,
-                           int walls, int want_p) {
-  hipLaunchKernelGGL(k_solve_pt, mode_grid(c, c->d.heated ? 2 : 1), dim3(256), 0, c->stream, c->d,
-                     c->g, c->fp, c->fp00, c->ft, reinterpret_cast<const double2 *>(c->s_g),
-                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<const double2 *>(nn),
-                     reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_p),
-                     reinterpret_cast<double2 *>(c->s_x) + (size_t)3 * c->d.nr * c->d.nmodes, cc,
-                     walls, want_p);
-  return hipGetLastError();
-}
-
-hipError_t launch_solve_vel(const nsc_ctx *c, int walls) {
-  hipLaunchKernelGGL(k_solve_vel, mode_grid(c, 3), dim3(256), 0, c->stream, c->d, c->g, c->fv,
-                     reinterpret_cast<const double2 *>(c->s_f), reinterpret_cast<const double2 *>(c->s_p),
-                     reinterpret_cast<double2 *>(c->s_x), walls);
-  return hipGetLastError();
-}
-
 hipError_t launch_influence(const nsc_ctx *c) {
   hipLaunchKernelGGL(k_influence, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->g, c->inf,
                      reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<double2 *>(c->s_lam));
@@ -1138,6 +1244,50 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
 hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout) {
   hipLaunchKernelGGL(k_energy_grad, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
                      reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(gout));
+  return hipGetLastError();
+}
+
+// stage 0: Poisson right side (+ temperature wall rows); 1: pressure and
+// temperature sweeps; 2: velocity right sides and sweeps.
+hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, const double *nq,
+                               double cc, int walls, int want_p) {
+  const Dims &d = c->d;
+  double2 *sf = reinterpret_cast<double2 *>(c->s_f);
+  double2 *sg = reinterpret_cast<double2 *>(c->s_g);
+  double2 *sp = reinterpret_cast<double2 *>(c->s_p);
+  double2 *sx = reinterpret_cast<double2 *>(c->s_x);
+  const int wp = (want_p && nn) ? 1 : 0;
+  const size_t col_bytes = (size_t)kSweepLanes * d.nr * sizeof(Cd);
+  const bool lds = col_bytes <= 64 * 1024;
+  const size_t shm = lds ? col_bytes : 0;
+  auto launch = [&](const SweepArgs &a, int nsys) {
+    dim3 gr((d.nmodes + kSweepLanes - 1) / kSweepLanes, nsys);
+    if (lds)
+      hipLaunchKernelGGL(k_sweep<true>, gr, dim3(kSweepLanes), shm, c->stream, d, a);
+    else
+      hipLaunchKernelGGL(k_sweep<false>, gr, dim3(kSweepLanes), 0, c->stream, d, a);
+  };
+  const size_t fld = (size_t)d.nr * d.nmodes;
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_div2, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sg,
+                       reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
+                       cc, wp);
+    if (d.heated)
+      hipLaunchKernelGGL(k_t_walls, mode_grid(c, 1), dim3(256), 0, c->stream, d, sf + 3 * fld, walls);
+  } else if (stage == 1) {
+    // pressure (s_g -> s_p) and temperature (s_f[3] -> s_x[3]) in one launch
+    SweepArgs a{};
+    a.s[0] = SweepSys{c->fp, c->fp00, 0, wp ? 1 : 2, sg, sp};
+    if (d.heated) a.s[1] = SweepSys{c->ft, c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
+    launch(a, d.heated ? 2 : 1);
+  } else {
+    hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls);
+    SweepArgs av{};
+    av.s[0] = SweepSys{c->fv, c->fv, 1, 0, sf, sx};
+    av.s[1] = SweepSys{c->fv, c->fv, 2, 0, sf + fld, sx + fld};
+    av.s[2] = SweepSys{c->fv, c->fv, 0, 0, sf + 2 * fld, sx + 2 * fld};
+    launch(av, 3);
+  }
   return hipGetLastError();
 }
 

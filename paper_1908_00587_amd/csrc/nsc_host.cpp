@@ -215,17 +215,18 @@ int solve_impl(nsc_ctx *c, const double *un, const double *nn, const double *nq,
     StageTimer t(c, 4);
     HIPCHK(launch_rhs(c, un, nn, nq, dt, cc));
   }
+  const int want_p = pout != nullptr;
   {
     StageTimer t(c, 5);
-    HIPCHK(launch_div(c));
+    HIPCHK(launch_solve_sweeps(c, 0, nn, nq, cc, walls, want_p));
   }
   {
     StageTimer t(c, 6);
-    HIPCHK(launch_solve_pt(c, nn, nq, cc, walls, pout != nullptr));
+    HIPCHK(launch_solve_sweeps(c, 1, nn, nq, cc, walls, want_p));
   }
   {
     StageTimer t(c, 7);
-    HIPCHK(launch_solve_vel(c, walls));
+    HIPCHK(launch_solve_sweeps(c, 2, nn, nq, cc, walls, want_p));
   }
   {
     StageTimer t(c, 8);
@@ -262,7 +263,7 @@ int nsc_destroy(nsc_ctx *c) {
   if (!c) return NSC_OK;
   void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
                   c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
-                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->inf.resp, c->inf.ainv};
+                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_factors(&c->fv);
@@ -319,6 +320,13 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return NSC_ERR_DEVICE;
   HIPCHK(hipGetDevice(&c->device));
+  {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
+            hipSuccess &&
+        lds >= 32 * 1024)
+      c->lds_max = lds - 1024;  // headroom for the kernels' static LDS
+  }
 
   // host tables
   const int n = d.nr;
@@ -348,7 +356,6 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   }
   cc_weights_host(n, ccw.data());
   for (int j = 0; j < n; ++j) ccw[j] *= 0.5;
-
   // device tables: one allocation
   const size_t nd = (size_t)n * (1 + 1 + kStencil * 2 + 1 + 1);
   TRY(dmalloc(&c->tables, nd * sizeof(double) + (size_t)n * sizeof(int) + 256));
@@ -401,6 +408,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   TRY(dmalloc((void **)&c->s_nq, field * d.f));
   TRY(dmalloc((void **)&c->s_tmp, field * d.f));
   TRY(dmalloc((void **)&c->s_adj, field * c->n_in));
+  TRY(dmalloc((void **)&c->s_mean, (size_t)8 * n * sizeof(double)));
   HIPCHK(hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault));
   HIPCHK(hipEventCreateWithFlags(&c->ev_cfl, hipEventDisableTiming));
   HIPCHK(hipEventCreate(&c->ev0));
@@ -505,10 +513,12 @@ int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
     HIPCHK(hipEventSynchronize(c->ev_cfl));
     const double dtc = c->h_pinned[0];
     if (std::isnan(dtc)) return NSC_ERR_NONFINITE;
-    double cand = c->cfl * dtc;
-    if (cand > c->dt_max) cand = c->dt_max;
+    // hysteresis: shrink to 0.9 of the bound when exceeded, grow (to 0.9 of
+    // the bound, capped by dt_max) only past +20 %
+    const double b = c->cfl * dtc;
     double next = dt;
-    if (cand < dt || cand > 1.1 * dt) next = cand;
+    if (b < dt) next = 0.9 * b;
+    else if ((b < c->dt_max ? b : c->dt_max) > 1.2 * dt) next = (0.9 * b < c->dt_max ? 0.9 * b : c->dt_max);
     if (!(next >= 1e-12)) return NSC_ERR_DT;
     *dt_inout = next;
   }

@@ -17,7 +17,7 @@ constexpr int kEdge = 20;      // extra U entries of rows 0..3 + extra L of rows
 constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 12;
 constexpr int kMaxFFT = 4096;
-constexpr int kFftThreads = 512;  // launch bound of the FFT kernels
+constexpr int kFftThreads = 1024;  // launch bound of the FFT kernels
 constexpr int kNumStages = 11;  // timed kernels (see nsc_get_timings)
 
 struct FftPlan {
@@ -75,6 +75,7 @@ struct nsc_ctx {
   double fac_dt = -1.0, fac_c = -1.0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int lds_max = 64 * 1024;  // dynamic LDS bytes per workgroup (device limit)
   // host copies
   double *h_r = nullptr;
   // device tables
@@ -104,6 +105,7 @@ struct nsc_ctx {
   double *s_nq = nullptr;   // [F][N_r][modes] complex N^q
   double *s_tmp = nullptr;  // [F][N_r][modes] complex scratch
   double *s_adj = nullptr;  // [n_in][N_r][modes] complex adjoint of the derived fields
+  double *s_mean = nullptr;  // [8][N_r] mean-flow profiles of the current nonlinear call
   double *h_pinned = nullptr;  // pinned host scalar(s)
   hipEvent_t ev_cfl = nullptr;
   // profiling
@@ -126,10 +128,8 @@ hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha,
 hipError_t launch_influence_setup(const nsc_ctx *c);
 hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn,
                       const double *nq, double dt, double cc);
-hipError_t launch_div(const nsc_ctx *c);
-hipError_t launch_solve_pt(const nsc_ctx *c, const double *nn, const double *nq,
-                           double cc, int walls, int want_p);
-hipError_t launch_solve_vel(const nsc_ctx *c, int walls);
+hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, const double *nq,
+                               double cc, int walls, int want_p);
 hipError_t launch_influence(const nsc_ctx *c);
 hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out);
 hipError_t launch_energy(const nsc_ctx *c, const double *u, double *e_dev);
