@@ -70,6 +70,21 @@ def kernel_bytes(name, w, prec):
     return 0
 
 
+def calibration_copy():
+    """A plain streaming kernel of known size (dst = -src: 256 MiB read,
+    256 MiB written) after a 1 GiB fill that evicts the caches, so that the
+    FETCH_SIZE / WRITE_SIZE counters of a profiled run can be scaled to bytes."""
+    import torch
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    evict = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    evict.fill_(2.0)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst, evict
+
+
 def run_gpu(args, wname):
     import torch
 
@@ -144,15 +159,44 @@ def run_gpu(args, wname):
                       if v[1] and kernel_bytes(k, w, "mixed") else None}
                   for k, v in tim.items()}
     ctx.close()
-    # calibration copy of known size (256 MiB read + 256 MiB written) so that
-    # hardware traffic counters of a profiled run can be scaled
-    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    del src, dst
+    calibration_copy()
     return dict(K=K, W=W, t64=t64, tmx=tmx, err=err, dt_end=(dt64, dtmx), dominant=kname,
                 avg_us=avg_s * 1e6, bytes=byt, achieved=achieved, per_kernel=per_kernel)
+
+
+def run_adjoint(steps, wname="tc-adjoint-n64", ckpt=20):
+    """Adjoint/forward cost ratio on the adjoint workload (eta = 0.71,
+    Re_i = 200, N_r = 64, 32 x 63 modes, dt = 5e-4): wall time of the
+    gradient pass (checkpoint recompute + vector-Jacobian products) over the
+    wall time of the plain forward rollout of the same steps."""
+    import torch
+
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout, rollout_energy
+    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+
+    w = WORKLOADS[wname]
+    ctx = nsc.Context(*params(wname))
+    u0 = ctx.initial_state(amplitudes(wname).cuda())
+    dt = w["dt"]
+    ctx.set_timestep(dt=dt)
+    rollout(ctx, u0, 4, dt)  # warm-up (factorisation)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rollout(ctx, u0, steps, dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    y = u0.clone().requires_grad_(True)
+    e = rollout_energy(ctx, y, steps, dt, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": wname, "steps": steps, "checkpoint_every": ckpt,
+            "forward_ms": round(1e3 * t_fwd, 3), "gradient_ms": round(1e3 * t_bwd, 3),
+            "ratio": round(t_bwd / t_fwd, 3)}
 
 
 def run_cpu(wname, steps):
@@ -173,7 +217,40 @@ def run_cpu(wname, steps):
                        f"{el:.1f} s")
 
 
+def pmc_summary(paths):
+    """Per-kernel average of each hardware counter over the dispatches of
+    rocprofv3 --pmc counter-collection CSV files (one line per kernel)."""
+    import csv
+    from collections import defaultdict
+    acc = defaultdict(lambda: defaultdict(list))
+    for path in paths:
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                name = row["Kernel_Name"]
+                short = name.replace("(anonymous namespace)::", "").split("(")[0]
+                if short.startswith("void "):
+                    short = short[5:]
+                if not short.startswith("nsc::"):
+                    # library kernels (copies, fills) are told apart by their
+                    # functor and size
+                    import re
+                    fun = re.findall(r"at::native::(?:\(anonymous namespace\)::)?(\w+)", name)
+                    tag = fun[1] if len(fun) > 1 else short
+                    short = tag[:30] + " grid=" + row["Grid_Size"]
+                acc[short][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    counters = sorted({c for k in acc.values() for c in k})
+    print("kernel".ljust(48) + "".join(c.rjust(14) for c in ["dispatches"] + counters))
+    for k in sorted(acc):
+        n = max(len(v) for v in acc[k].values())
+        cells = [str(n)] + [f"{sum(acc[k][c]) / len(acc[k][c]):.6g}" if acc[k].get(c) else "-"
+                            for c in counters]
+        print(k[:48].ljust(48) + "".join(x.rjust(14) for x in cells))
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--pmc-summary":
+        pmc_summary(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -181,6 +258,7 @@ def main():
     ap.add_argument("--workload", default="tc-heated-n64")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a "
@@ -189,6 +267,7 @@ def main():
     from paper_1908_00587_amd.workloads import WORKLOADS
     w = WORKLOADS[args.workload]
     g = run_gpu(args, args.workload)
+    adj = run_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
     cpu = None if args.no_cpu else run_cpu(args.workload, args.cpu_steps)
     K = g["K"]
     mx_sps = K / g["tmx"]
@@ -219,6 +298,7 @@ def main():
                      "achieved": round(g["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(g["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": g["bytes"], "avg_launch_us": round(g["avg_us"], 3)},
+        "adjoint_forward_cost_ratio": adj,
         "kernels": g["per_kernel"],
         "cpu_baseline": cpu,
     }

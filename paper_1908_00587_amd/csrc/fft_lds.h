@@ -161,22 +161,36 @@ __device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
   const int nb = n / R;
   const int total = nlines * nb;
   const int step = n / (ns * R);
+  const bool pow2 = (ns & (ns - 1)) == 0;
+  const float inb = 1.0f / (float)nb;
+  int jj[MAXB], ll[MAXB];
   C2<T> v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
     const int b = threadIdx.x + q * blockDim.x;
     if (b < total) {
-      const int line = b / nb;
-      const int j = b - line * nb;
-      const int k = j % ns;
+      int line = (int)(((float)b + 0.5f) * inb);
+      int j = b - line * nb;
+      if (j < 0) {
+        --line;
+        j += nb;
+      } else if (j >= nb) {
+        ++line;
+        j -= nb;
+      }
+      jj[q] = j;
+      ll[q] = line;
+      const int k = pow2 ? (j & (ns - 1)) : (j % ns);
       const C2<T> *L = buf + line * ls;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = L[j + r * nb];
+      if (ns > 1) {  // the first stage has unit twiddles
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        C2<T> w = tw[r * k * step];
-        if (INV) w.y = -w.y;
-        v[q][r] = cmul(v[q][r], w);
+        for (int r = 1; r < R; ++r) {
+          C2<T> w = tw[r * k * step];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
       }
       Dft<T, R, INV>::run(v[q]);
     }
@@ -186,11 +200,10 @@ __device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
   for (int q = 0; q < MAXB; ++q) {
     const int b = threadIdx.x + q * blockDim.x;
     if (b < total) {
-      const int line = b / nb;
-      const int j = b - line * nb;
-      const int k = j % ns;
-      C2<T> *L = buf + line * ls;
-      const int base = (j / ns) * ns * R + k;
+      const int j = jj[q];
+      const int k = pow2 ? (j & (ns - 1)) : (j % ns);
+      C2<T> *L = buf + ll[q] * ls;
+      const int base = (j - k) * R + k;  // (j / ns) ns R + j mod ns
 #pragma unroll
       for (int r = 0; r < R; ++r) L[base + r * ns] = v[q][r];
     }
@@ -223,6 +236,116 @@ __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
       }
       ns *= R;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-scope transforms.  The lines belong to one wavefront, which alone
+// reads and writes them.  The LDS executes the instructions of a wavefront in
+// program order, so a stage needs no workgroup barrier: a compiler-level
+// barrier keeps the reads of a stage ahead of its writes and stops values
+// from being held in registers across stages.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One Stockham stage over `nlines` lines of one wavefront; every butterfly of
+// the lane is held in registers between the read and the write phase
+// (host guarantee: nlines * n / R <= 64 * (kWaveRegs / R)).
+template <typename T, int R, bool INV>
+__device__ __attribute__((noinline)) void wave_stage(C2<T> *buf, int nlines, int n, int ls, int ns,
+                                           const C2<T> *tw, int lane) {
+  constexpr int MW = kWaveRegs / R;
+  const int nb = n / R;
+  const int total = nlines * nb;
+  const int step = n / (ns * R);
+  const bool pow2 = (ns & (ns - 1)) == 0;
+  const float inb = 1.0f / (float)nb;
+  C2<T> v[MW][R];
+  int wa[MW];
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    const int b = lane + 64 * q;
+    if (b < total) {
+      int line = (int)(((float)b + 0.5f) * inb);
+      int j = b - line * nb;
+      if (j < 0) {
+        --line;
+        j += nb;
+      } else if (j >= nb) {
+        ++line;
+        j -= nb;
+      }
+      const int k = pow2 ? (j & (ns - 1)) : (j % ns);
+      const C2<T> *L = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = L[j + r * nb];
+      if (ns > 1) {  // the first stage has unit twiddles
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C2<T> w = tw[r * k * step];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Dft<T, R, INV>::run(v[q]);
+      wa[q] = line * ls + (j - k) * R + k;
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    if (lane + 64 * q < total) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[wa[q] + r * ns] = v[q][r];
+    }
+  }
+  wave_sync();
+}
+
+// Transform of `nlines` lines owned by one wavefront, in groups of
+// plan.wave_lines lines.  Forward (e^{-}) or inverse (e^{+}), unnormalised.
+template <typename T, bool INV>
+__device__ void fft_wave(C2<T> *buf, int nlines, int ls, const FftPlan &plan, const C2<T> *tw,
+                         int lane) {
+  const int n = plan.n;
+  const int gl = plan.wave_lines;
+  for (int l0 = 0; l0 < nlines; l0 += gl) {
+    const int nl = nlines - l0 < gl ? nlines - l0 : gl;
+    C2<T> *b0 = buf + l0 * ls;
+    int ns = 1;
+    for (int s = 0; s < plan.nst; ++s) {
+      const int R = plan.radix[s];
+      switch (R) {
+        case 2: wave_stage<T, 2, INV>(b0, nl, n, ls, ns, tw, lane); break;
+        case 3: wave_stage<T, 3, INV>(b0, nl, n, ls, ns, tw, lane); break;
+        case 4: wave_stage<T, 4, INV>(b0, nl, n, ls, ns, tw, lane); break;
+        case 5: wave_stage<T, 5, INV>(b0, nl, n, ls, ns, tw, lane); break;
+        default: wave_stage<T, 8, INV>(b0, nl, n, ls, ns, tw, lane); break;
+      }
+      ns *= R;
+    }
+  }
+}
+
+// The nl lines of a workgroup: with a wavefront-scope plan each wavefront
+// transforms a contiguous share of them and the workgroup meets once at the
+// end; otherwise the whole workgroup works on each group of lines together.
+template <typename T, bool INV, int MAXB>
+__device__ __forceinline__ void fft_block(C2<T> *buf, int nl, int ls, const FftPlan &plan,
+                                          const C2<T> *tw) {
+  if (plan.wave_lines > 0) {
+    const int nw = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
+    const int per = (nl + nw - 1) / nw;
+    const int l0 = w * per;
+    const int cnt = nl - l0 < per ? nl - l0 : per;
+    if (cnt > 0) fft_wave<T, INV>(buf + l0 * ls, cnt, ls, plan, tw, (int)(threadIdx.x & 63));
+    __syncthreads();
+  } else {
+    fft_lines<T, INV, MAXB>(buf, nl, ls, plan, tw);
   }
 }
 

@@ -90,25 +90,28 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax;
-  const int ls = nz + 1;
+  const int ls = (nz + 1);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int li = idx / nz;
-    const int b = idx - li * nz;
-    C2<T> val = {T(0), T(0)};
-    int k = INT_MIN;
-    if (b <= K) k = b;
-    else if (b >= nz - K) k = b - nz;
-    if (k != INT_MIN) {
-      double2 v = derived(d, g, u, f, j, mt0 + li, k + K, drop_mean != 0);
-      val = {T(v.x), T(v.y)};
-    }
-    buf[li * ls + b] = val;
+  // retained modes: one item per (line, k) so that every thread's loads are
+  // independent and issued together; then the zero padding
+  const int mz = d.mz;
+  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
+    const int li = idx / mz;
+    const int kk = idx - li * mz;
+    const int k = kk - K;
+    const double2 v = derived(d, g, u, f, j, mt0 + li, kk, drop_mean != 0);
+    buf[li * ls + (k >= 0 ? k : nz + k)] = {T(v.x), T(v.y)};
+  }
+  const int npad = nz - mz;
+  for (int idx = threadIdx.x; idx < nl * npad; idx += blockDim.x) {
+    const int li = idx / npad;
+    const int b = K + 1 + (idx - li * npad);
+    buf[li * ls + b] = {T(0), T(0)};
   }
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = Z + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -117,66 +120,124 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   }
 }
 
+// Lines p = 0..np-1 of buf: Z_m = F_{2p,m} + i F_{2p+1,m} for 0 < m < M_theta,
+// Z_{N-m} = conj F_{2p,m} + i conj F_{2p+1,m}, Z_0 = Re F_{2p,0} + i Re F_{2p+1,0},
+// zero elsewhere, so that the inverse FFT yields the two real fields.
 template <typename T>
-__device__ __forceinline__ C2<T> ldz(const C2<T> *__restrict__ p) { return *p; }
+__device__ __forceinline__ void pack_pairs(C2<T> *buf, int ls, const C2<T> *__restrict__ zl,
+                                           size_t fstride, int nf, int np, int nt, int mt,
+                                           int gt, int gsz) {
+  for (int idx = gt; idx < np * mt; idx += gsz) {
+    const int p = idx / mt;
+    const int m = idx - p * mt;
+    const int f1 = 2 * p, f2 = 2 * p + 1;
+    const C2<T> F1 = zl[f1 * fstride + m];
+    const C2<T> F2 = f2 < nf ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
+    C2<T> *L = buf + p * ls;
+    if (m == 0) {
+      L[0] = {F1.x, F2.x};
+    } else {
+      L[m] = {F1.x - F2.y, F1.y + F2.x};
+      L[nt - m] = {F1.x + F2.y, F2.x - F1.y};
+    }
+  }
+  const int nzero = nt - 2 * mt + 1;
+  for (int idx = gt; idx < np * nzero; idx += gsz) {
+    const int p = idx / nzero;
+    buf[p * ls + mt + (idx - p * nzero)] = {T(0), T(0)};
+  }
+}
 
-template <typename T>
+// Work group of the theta pass: with WAVE one wavefront per (r, z) line set
+// (several sets per workgroup, no workgroup barrier after the twiddle load),
+// otherwise the whole workgroup on one set.
+struct ThetaGroup {
+  int set, gt, gsz, slot;
+};
+
+template <bool WAVE>
+__device__ __forceinline__ ThetaGroup theta_group() {
+  ThetaGroup t;
+  if (WAVE) {
+    const int nw = (int)(blockDim.x >> 6);
+    t.slot = (int)(threadIdx.x >> 6);
+    t.set = xcd_remap((int)blockIdx.x, (int)gridDim.x) * nw + t.slot;
+    t.gt = (int)(threadIdx.x & 63);
+    t.gsz = 64;
+  } else {
+    int bx, by, unused;
+    xcd_block(bx, by, unused);
+    t.set = by * (int)gridDim.x + bx;
+    t.slot = 0;
+    t.gt = (int)threadIdx.x;
+    t.gsz = (int)blockDim.x;
+  }
+  return t;
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void group_sync() {
+  if (WAVE) wave_sync();
+  else __syncthreads();
+}
+
+template <typename T, bool WAVE, bool INV>
+__device__ __forceinline__ void group_fft(C2<T> *buf, int nl, int ls, const FftPlan &p,
+                                          const C2<T> *tw, int gt) {
+  if (WAVE) fft_wave<T, INV>(buf, nl, ls, p, tw, gt);
+  else fft_lines<T, INV, kMaxB>(buf, nl, ls, p, tw);
+}
+
+template <typename T, bool WAVE>
 __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
                         C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
                         double dth, double dzs, double *__restrict__ cfl_part,
                         int want_cfl, const double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nt;
-  __shared__ double red[kFftThreads / 64];
+  __shared__ double red[3 * (kFftThreads / 64)];
   const int nt = d.nt, mt = d.mt;
-  const int ls = nt + 1;
-  int b, j, unused;
-  xcd_block(b, j, unused);  // b: z index, j: radial row
-  load_twiddles(tws, tw, nt);
+  const int ls = (nt + 1);
   const int npi = (n_in + 1) / 2;
+  const ThetaGroup grp = theta_group<WAVE>();
+  const int gt = grp.gt, gsz = grp.gsz;
+  load_twiddles(tws, tw, nt);
+  __syncthreads();
+  if (grp.set >= d.nz * d.nr) return;  // wavefronts past the last set (WAVE only)
+  const int j = grp.set / d.nz, b = grp.set - j * d.nz;  // radial row, z index
+  C2<T> *buf = tws + nt + (size_t)grp.slot * npi * ls;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   const C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
-  // pack pairs of real fields into Hermitian-extended complex lines
-  for (int idx = threadIdx.x; idx < npi * nt; idx += blockDim.x) {
-    const int p = idx / nt;
-    const int a = idx - p * nt;
-    const int f1 = 2 * p, f2 = 2 * p + 1;
-    C2<T> v = {T(0), T(0)};
-    if (a == 0) {
-      C2<T> F1 = zl[f1 * fstride];
-      C2<T> F2 = f2 < n_in ? zl[f2 * fstride] : C2<T>{T(0), T(0)};
-      v = {F1.x, F2.x};
-    } else if (a < mt) {
-      C2<T> F1 = zl[f1 * fstride + a];
-      C2<T> F2 = f2 < n_in ? zl[f2 * fstride + a] : C2<T>{T(0), T(0)};
-      v = {F1.x - F2.y, F1.y + F2.x};
-    } else if (a > nt - mt) {
-      const int m = nt - a;
-      C2<T> F1 = zl[f1 * fstride + m];
-      C2<T> F2 = f2 < n_in ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
-      v = {F1.x + F2.y, F2.x - F1.y};
-    }
-    buf[p * ls + a] = v;
-  }
-  __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, npi, ls, pt, tws);
+  // pack pairs of real fields into Hermitian-extended complex lines: one
+  // item per (pair, m) fills positions m and N_theta - m
+  pack_pairs(buf, ls, zl, fstride, n_in, npi, nt, mt, gt, gsz);
+  group_sync<WAVE>();
+  group_fft<T, WAVE, true>(buf, npi, ls, pt, tws, gt);
   // pointwise products and CFL bound
-  const double rj = g.r[j], drj = g.dr[j];
+  // CFL: the spacings are constant along the line set, so the smallest
+  // Delta_i / |u_i| is Delta_i / max |u_i| (the same rounded value): the
+  // maxima are reduced and three divisions close the set
   const double mur = mean[j], mut = mean[d.nr + j], muz = mean[2 * d.nr + j];
-  double lmin = DBL_MAX;
+  const int nr = d.nr;
+  const T mU = T(mur), mV = T(mut), mW = T(muz), mOt = T(mean[4 * nr + j]),
+          mOz = T(mean[5 * nr + j]), mG = T(mean[6 * nr + j]);
+  double xr = 0.0, xt = 0.0, xz = 0.0;  // running max |u_r|, |u_theta|, |u_z|
   bool bad = false;
   const bool heated = n_in > 6;
-  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
+  for (int a = gt; a < nt; a += gsz) {
     C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
     const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
-    const T nr_ = ut * wz - uz * wt;
-    const T nth = uz * wr - ur * wz;
-    const T nzz = ur * wt - ut * wr;
+    // u' x omega' + U x omega' + u' x Omega (Omega_r = 0); U x Omega is exact
+    // in mode (0,0)
+    const T nr_ = (ut * wz - uz * wt) + (mV * wz - mW * wt) + (ut * mOz - uz * mOt);
+    const T nth = (uz * wr - ur * wz) + (mW * wr - mU * wz) - ur * mOz;
+    const T nzz = (ur * wt - ut * wr) + (mU * wt - mV * wr) + ur * mOt;
     T ntt = T(0);
     if (heated) {
+      // -(u' . grad T' + U . grad T' + u_r' dT_m/dr); -U_r dT_m/dr in mode (0,0)
       C2<T> l3 = buf[3 * ls + a], l4 = buf[4 * ls + a];
-      ntt = -(ur * l3.x + ut * l3.y + uz * l4.x);
+      ntt = -((ur * l3.x + ut * l3.y + uz * l4.x) + (mU * l3.x + mV * l3.y + mW * l4.x) +
+              ur * mG);
     }
     buf[a] = {nr_, nth};
     buf[ls + a] = {nzz, ntt};
@@ -184,17 +245,17 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
       const double aur = fabs((double)ur + mur), aut = fabs((double)ut + mut),
                    auz = fabs((double)uz + muz);
       if (!(isfinite(aur) && isfinite(aut) && isfinite(auz))) bad = true;
-      if (aur > 0.0) lmin = fmin(lmin, drj / aur);
-      if (aut > 0.0) lmin = fmin(lmin, rj * dth / aut);
-      if (auz > 0.0) lmin = fmin(lmin, dzs / auz);
+      xr = fmax(xr, aur);
+      xt = fmax(xt, aut);
+      xz = fmax(xz, auz);
     }
   }
-  __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, 2, ls, pt, tws);
+  group_sync<WAVE>();
+  group_fft<T, WAVE, false>(buf, 2, ls, pt, tws, gt);
   // unpack the two real transforms of each line, keep m < M_theta
   const int nout = heated ? 4 : 3;
   C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
-  for (int idx = threadIdx.x; idx < 2 * mt; idx += blockDim.x) {
+  for (int idx = gt; idx < 2 * mt; idx += gsz) {
     const int p = idx / mt;
     const int m = idx - p * mt;
     const C2<T> zm = buf[p * ls + m];
@@ -206,64 +267,66 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
     if (2 * p + 1 < nout) wl[(size_t)(2 * p + 1) * fstride + m] = y;
   }
   if (want_cfl) {
-    if (bad) lmin = NAN;
-    // wave reduction then block reduction (min, NaN-propagating)
+    if (bad) xr = NAN;
+    // wavefront reduction (max, NaN-propagating), then across the workgroup
+    auto mx = [](double a, double b) { return (isnan(a) || isnan(b)) ? NAN : fmax(a, b); };
     for (int off = 32; off > 0; off >>= 1) {
-      double o = __shfl_down(lmin, off, 64);
-      lmin = (isnan(o) || isnan(lmin)) ? NAN : fmin(lmin, o);
+      xr = mx(xr, __shfl_down(xr, off, 64));
+      xt = mx(xt, __shfl_down(xt, off, 64));
+      xz = mx(xz, __shfl_down(xz, off, 64));
     }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) red[wid] = lmin;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = red[0];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-        v = (isnan(v) || isnan(red[w])) ? NAN : fmin(v, red[w]);
-      cfl_part[(size_t)j * gridDim.x + b] = v;
+    auto bound = [&](double ar, double at, double az) {
+      if (isnan(ar)) return (double)NAN;
+      double v = DBL_MAX;
+      if (ar > 0.0) v = fmin(v, g.dr[j] / ar);
+      if (at > 0.0) v = fmin(v, g.r[j] * dth / at);
+      if (az > 0.0) v = fmin(v, dzs / az);
+      return v;
+    };
+    if (WAVE) {
+      if (gt == 0) cfl_part[grp.set] = bound(xr, xt, xz);
+    } else {
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+      if (lane == 0) {
+        red[wid] = xr;
+        red[16 + wid] = xt;
+        red[32 + wid] = xz;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double ar = red[0], at = red[16], az = red[32];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+          ar = mx(ar, red[w]);
+          at = mx(at, red[16 + w]);
+          az = mx(az, red[32 + w]);
+        }
+        cfl_part[grp.set] = bound(ar, at, az);
+      }
     }
   }
 }
 
-// Terms of output field f at (j, m, kk) that involve the mean flow (mode
-// (0,0), r only): mean x mean, mean x omega', u' x mean vorticity,
-// -mean . grad T', -u' . grad T_mean, formed exactly per mode; plus the
-// buoyancy Gr T.  mean[.][j]: U_r, V, W, T_m, Om_theta = -D1 W,
-// Om_z = D1 V + V/r, G = D1 T_m.
-__device__ __forceinline__ double2 mean_terms(const Dims &d, const Grid &g,
-                                              const double2 *__restrict__ u,
-                                              const double *__restrict__ mean, int f, int j,
-                                              int m, int kk) {
+// Spectral terms added to output field f at (j, m, kk): in mode (0,0) the
+// mean-flow products U x Omega and -U_r dT_m/dr (r only, formed exactly),
+// and the buoyancy Gr T in the axial component.  mean[.][j]: U_r, V, W, T_m,
+// Om_theta = -D1 W, Om_z = D1 V + V/r, G = D1 T_m.
+__device__ __forceinline__ double2 spectral_terms(const Dims &d, const double2 *__restrict__ u,
+                                                  const double *__restrict__ mean, int f, int j,
+                                                  int m, int kk) {
   const int n = d.nr;
-  const double Ur = mean[j], V = mean[n + j], W = mean[2 * n + j];
-  const double Ot = mean[4 * n + j], Oz = mean[5 * n + j];
-  const bool b00 = (m == 0 && kk == d.kmax);
-  auto D = [&](int fld) { return derived(d, g, u, fld, j, m, kk, true); };
-  auto lin = [](double a, double2 x, double b, double2 y) {
-    return make_double2(a * x.x + b * y.x, a * x.y + b * y.y);
-  };
   double2 o = make_double2(0.0, 0.0);
-  if (f == 0) {
-    const double2 a = lin(V, D(5), -W, D(4)), b = lin(Oz, D(1), -Ot, D(2));
-    o = make_double2(a.x + b.x, a.y + b.y);
-    if (b00) o.x += V * Oz - W * Ot;
-  } else if (f == 1) {
-    const double2 a = lin(W, D(3), -Ur, D(5)), b = D(0);
-    o = make_double2(a.x - Oz * b.x, a.y - Oz * b.y);
-    if (b00) o.x -= Ur * Oz;
-  } else if (f == 2) {
-    const double2 a = lin(Ur, D(4), -V, D(3)), b = D(0);
-    o = make_double2(a.x + Ot * b.x, a.y + Ot * b.y);
-    if (b00) o.x += Ur * Ot;
-    if (d.heated) {
-      const double2 t = u[((size_t)3 * n + j) * d.nmodes + (size_t)m * d.mz + kk];
-      o.x += d.gr * t.x;
-      o.y += d.gr * t.y;
-    }
-  } else {
-    const double G = mean[6 * n + j];
-    const double2 a = lin(Ur, D(6), V, D(7)), b = lin(W, D(8), G, D(0));
-    o = make_double2(-(a.x + b.x), -(a.y + b.y));
-    if (b00) o.x -= Ur * G;
+  if (m == 0 && kk == d.kmax) {
+    const double Ur = mean[j], V = mean[n + j], W = mean[2 * n + j];
+    const double Ot = mean[4 * n + j], Oz = mean[5 * n + j], G = mean[6 * n + j];
+    if (f == 0) o.x = V * Oz - W * Ot;
+    else if (f == 1) o.x = -Ur * Oz;
+    else if (f == 2) o.x = Ur * Ot;
+    else o.x = -Ur * G;
+  }
+  if (f == 2 && d.heated) {
+    const double2 t = u[((size_t)3 * n + j) * d.nmodes + (size_t)m * d.mz + kk];
+    o.x += d.gr * t.x;
+    o.y += d.gr * t.y;
   }
   return o;
 }
@@ -304,7 +367,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = nz + 1;
+  const int ls = (nz + 1);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
@@ -315,7 +378,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
     buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
   for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
     const int li = idx / mz;
@@ -323,13 +386,13 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
     const int m = mt0 + li;
     const int k = kk - K;
     const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
-    const double2 bt = mean_terms(d, g, u, mean, f, j, m, kk);
+    const double2 bt = spectral_terms(d, u, mean, f, j, m, kk);
     double2 o = {(double)v.x * scale + bt.x, (double)v.y * scale + bt.y};
     const size_t md = (size_t)m * mz + kk;
     if (m == 0) {
       const int kkm = mz - 1 - kk;
       const C2<T> vm = buf[li * ls + (k <= 0 ? -k : nz - k)];
-      const double2 bm = mean_terms(d, g, u, mean, f, j, m, kkm);
+      const double2 bm = spectral_terms(d, u, mean, f, j, m, kkm);
       const double2 om = {(double)vm.x * scale + bm.x, (double)vm.y * scale + bm.y};
       o = {0.5 * (o.x + om.x), 0.5 * (o.y - om.y)};
     }
@@ -378,34 +441,32 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = nz + 1;
+  const int ls = (nz + 1);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
   const size_t plane = (size_t)d.nmodes;
   const double2 *src = nb + ((size_t)f * d.nr + j) * plane;
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int li = idx / nz;
-    const int b = idx - li * nz;
-    C2<T> val = {T(0), T(0)};
-    int k = INT_MIN;
-    if (b <= K) k = b;
-    else if (b >= nz - K) k = b - nz;
-    if (k != INT_MIN) {
-      const int m = mt0 + li;
-      const int kk = k + K;
-      double2 v = src[(size_t)m * mz + kk];
-      if (m == 0) {
-        const double2 w = src[mz - 1 - kk];
-        v = make_double2(0.5 * (v.x + w.x), 0.5 * (v.y - w.y));
-      }
-      const double s = (m == 0 ? 1.0 : 0.5) * scale;
-      val = {T(v.x * s), T(v.y * s)};
+  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
+    const int li = idx / mz;
+    const int kk = idx - li * mz;
+    const int k = kk - K;
+    const int m = mt0 + li;
+    double2 v = src[(size_t)m * mz + kk];
+    if (m == 0) {
+      const double2 w = src[mz - 1 - kk];
+      v = make_double2(0.5 * (v.x + w.x), 0.5 * (v.y - w.y));
     }
-    buf[li * ls + b] = val;
+    const double s = (m == 0 ? 1.0 : 0.5) * scale;
+    buf[li * ls + (k >= 0 ? k : nz + k)] = {T(v.x * s), T(v.y * s)};
+  }
+  const int npad = nz - mz;
+  for (int idx = threadIdx.x; idx < nl * npad; idx += blockDim.x) {
+    const int li = idx / npad;
+    buf[li * ls + K + 1 + (idx - li * npad)] = {T(0), T(0)};
   }
   __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = W + ((size_t)f * d.nr + j) * nz * d.mt;
   for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
     const int b = idx / nl;
@@ -414,53 +475,33 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void pack_line(C2<T> *L, const C2<T> *zl, size_t fstride, int f1, int f2,
-                                          int nf, int nt, int mt) {
-  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
-    C2<T> v = {T(0), T(0)};
-    if (a == 0) {
-      C2<T> F1 = zl[f1 * fstride];
-      C2<T> F2 = f2 < nf ? zl[f2 * fstride] : C2<T>{T(0), T(0)};
-      v = {F1.x, F2.x};
-    } else if (a < mt) {
-      C2<T> F1 = zl[f1 * fstride + a];
-      C2<T> F2 = f2 < nf ? zl[f2 * fstride + a] : C2<T>{T(0), T(0)};
-      v = {F1.x - F2.y, F1.y + F2.x};
-    } else if (a > nt - mt) {
-      const int m = nt - a;
-      C2<T> F1 = zl[f1 * fstride + m];
-      C2<T> F2 = f2 < nf ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
-      v = {F1.x + F2.y, F2.x - F1.y};
-    }
-    L[a] = v;
-  }
-}
-
 // Per (r, z) line: forward fields from Z, adjoint outputs from W; pointwise
 // adjoint products; forward theta FFT of the input adjoints back into Z.
-template <typename T>
+template <typename T, bool WAVE>
 __global__ void __launch_bounds__(kFftThreads)
 k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
             const C2<T> *__restrict__ tw, int n_in, int n_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nt;
   const int nt = d.nt, mt = d.mt;
-  const int ls = nt + 1;
-  int b, j, unused;
-  xcd_block(b, j, unused);
-  load_twiddles(tws, tw, nt);
+  const int ls = (nt + 1);
   const int npi = (n_in + 1) / 2;
+  const ThetaGroup grp = theta_group<WAVE>();
+  const int gt = grp.gt, gsz = grp.gsz;
+  load_twiddles(tws, tw, nt);
+  __syncthreads();
+  if (grp.set >= d.nz * d.nr) return;
+  const int j = grp.set / d.nz, b = grp.set - j * d.nz;
+  C2<T> *buf = tws + nt + (size_t)grp.slot * (npi + 2) * ls;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
   const C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
-  for (int p = 0; p < npi; ++p) pack_line(buf + p * ls, zl, fstride, 2 * p, 2 * p + 1, n_in, nt, mt);
-  for (int p = 0; p < 2; ++p) pack_line(buf + (npi + p) * ls, wl, fstride, 2 * p, 2 * p + 1, n_out, nt, mt);
-  __syncthreads();
-  fft_lines<T, true, kMaxB>(buf, npi + 2, ls, pt, tws);
+  pack_pairs(buf, ls, zl, fstride, n_in, npi, nt, mt, gt, gsz);
+  pack_pairs(buf + npi * ls, ls, wl, fstride, n_out, 2, nt, mt, gt, gsz);
+  group_sync<WAVE>();
+  group_fft<T, WAVE, true>(buf, npi + 2, ls, pt, tws, gt);
   const bool heated = n_in > 6;
-  for (int a = threadIdx.x; a < nt; a += blockDim.x) {
+  for (int a = gt; a < nt; a += gsz) {
     const C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
     const C2<T> n0 = buf[npi * ls + a], n1 = buf[(npi + 1) * ls + a];
     const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
@@ -483,9 +524,9 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
     buf[ls + a] = {buz, bwr};
     buf[2 * ls + a] = {bwt, bwz};
   }
-  __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, npi, ls, pt, tws);
-  for (int idx = threadIdx.x; idx < npi * mt; idx += blockDim.x) {
+  group_sync<WAVE>();
+  group_fft<T, WAVE, false>(buf, npi, ls, pt, tws, gt);
+  for (int idx = gt; idx < npi * mt; idx += gsz) {
     const int p = idx / mt;
     const int m = idx - p * mt;
     const C2<T> zm = buf[p * ls + m];
@@ -508,7 +549,7 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = nz + 1;
+  const int ls = (nz + 1);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
@@ -519,7 +560,7 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
     buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_lines<T, false, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
   for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
     const int li = idx / mz;
@@ -616,11 +657,56 @@ int z_lines(const nsc_ctx *c, size_t esize) {
   return tm;
 }
 
+// Threads of a z-pass workgroup of tm lines: with a wavefront-scope plan,
+// wavefronts of up to four lines each; otherwise the block-scope rule.
+int z_threads(const FftPlan &p, int tm) {
+  if (p.wave_lines > 0) {
+    const int per = p.wave_lines < 4 ? p.wave_lines : 4;
+    int nw = (tm + per - 1) / per;
+    if (nw > kFftThreads / 64) nw = kFftThreads / 64;
+    return 64 * nw;
+  }
+  return block_for(p, tm, 256);
+}
+
+// Theta-pass launch shape: wavefront-scope sets when the plan allows it and
+// a set's lines fit a modest LDS share, else one set per workgroup.
+struct ThetaLaunch {
+  bool wave;
+  int waves;      // sets per workgroup (wave mode)
+  dim3 grid;
+  int threads;
+  size_t shm;
+};
+
+ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize) {
+  ThetaLaunch L;
+  const size_t line = (size_t)(c->d.nt + 1) * esize;
+  const size_t tws = (size_t)c->d.nt * esize;
+  const int nsets = c->d.nz * c->d.nr;
+  L.wave = c->plan_t.wave_lines > 0 && (size_t)nlines * line <= 24 * 1024;
+  if (L.wave) {
+    int w = (int)(((size_t)c->lds_max - tws) / ((size_t)nlines * line));
+    if (w > 4) w = 4;
+    if (w < 1) w = 1;
+    L.waves = w;
+    L.grid = dim3((nsets + w - 1) / w);
+    L.threads = 64 * w;
+    L.shm = tws + (size_t)w * nlines * line;
+  } else {
+    L.waves = 1;
+    L.grid = dim3(c->d.nz, c->d.nr);
+    L.threads = block_for(c->plan_t, nlines, 256);
+    L.shm = tws + (size_t)nlines * line;
+  }
+  return L;
+}
+
 template <typename T>
 hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
-  const int threads = block_for(c->plan_z, tm, 256);
+  const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
   hipLaunchKernelGGL(k_mean, dim3((c->d.nr + 63) / 64), dim3(64), 0, c->stream, c->d, c->g,
                      reinterpret_cast<const double2 *>(u), c->s_mean);
@@ -633,13 +719,12 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
 
 template <typename T>
 hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
-  dim3 grid(c->d.nz, c->d.nr);
   const int npi = (c->n_in + 1) / 2;
-  const int threads = block_for(c->plan_t, npi, 256);
-  const size_t shm = ((size_t)npi * (c->d.nt + 1) + c->d.nt) * sizeof(C2<T>);
+  const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>));
   const double dth = 2.0 * M_PI / c->d.nt;
   const double dzs = c->d.lz / c->d.nz;
-  hipLaunchKernelGGL(k_theta<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
+  auto kern = L.wave ? k_theta<T, true> : k_theta<T, false>;
+  hipLaunchKernelGGL(kern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->g,
                      c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
                      reinterpret_cast<C2<T> *>(c->wbuf),
                      reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
@@ -651,7 +736,7 @@ template <typename T>
 hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
-  const int threads = block_for(c->plan_z, tm, 256);
+  const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
   hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->g, c->plan_z,
@@ -666,7 +751,7 @@ template <typename T>
 hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *nbar, double *ubar,
                               const T *twz, const T *twt) {
   const int tm = z_lines(c, sizeof(C2<T>));
-  const int zthreads = block_for(c->plan_z, tm, 256);
+  const int zthreads = z_threads(c->plan_z, tm);
   const size_t zshm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
   // forward fields on the (r, theta-spectral, z-physical) grid
   hipLaunchKernelGGL(k_zinv<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads), zshm,
@@ -678,9 +763,9 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
                      reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twz), tm,
                      scale);
   const int npi = (c->n_in + 1) / 2;
-  const int tthreads = block_for(c->plan_t, npi + 2, 256);
-  const size_t tshm = ((size_t)(npi + 2) * (c->d.nt + 1) + c->d.nt) * sizeof(C2<T>);
-  hipLaunchKernelGGL(k_theta_adj<T>, dim3(c->d.nz, c->d.nr), dim3(tthreads), tshm, c->stream, c->d,
+  const ThetaLaunch L = theta_launch(c, npi + 2, sizeof(C2<T>));
+  auto tkern = L.wave ? k_theta_adj<T, true> : k_theta_adj<T, false>;
+  hipLaunchKernelGGL(tkern, L.grid, dim3(L.threads), L.shm, c->stream, c->d,
                      c->plan_t, reinterpret_cast<C2<T> *>(c->zbuf),
                      reinterpret_cast<const C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twt),
                      c->n_in, c->n_out);

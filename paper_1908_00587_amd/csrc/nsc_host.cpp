@@ -22,24 +22,39 @@ namespace {
 // ---------------------------------------------------------------------------
 bool plan_fft(int n, FftPlan *p) {
   if (n < 2 || n > kMaxFFT) return false;
+  // power-of-two radices first, so that the accumulated length of every
+  // stage up to the radix-3 one is a power of two (mask instead of modulo)
   int rem = n;
   int nst = 0;
   int r[kMaxStages];
-  while (rem % 5 == 0) { rem /= 5; r[nst++] = 5; }
-  while (rem % 3 == 0) { rem /= 3; r[nst++] = 3; }
-  int a = 0;
+  int n3 = 0, n5 = 0, a = 0;
+  while (rem % 5 == 0) { rem /= 5; ++n5; }
+  while (rem % 3 == 0) { rem /= 3; ++n3; }
   while (rem % 2 == 0) { rem /= 2; ++a; }
   if (rem != 1) return false;
-  while (a >= 3 && a != 4) { r[nst++] = 8; a -= 3; }
-  while (a >= 2) { r[nst++] = 4; a -= 2; }
-  if (a == 1) r[nst++] = 2;
-  if (nst > kMaxStages) return false;
+  while (a >= 3 && a != 4) { if (nst >= kMaxStages) return false; r[nst++] = 8; a -= 3; }
+  while (a >= 2) { if (nst >= kMaxStages) return false; r[nst++] = 4; a -= 2; }
+  if (a == 1) { if (nst >= kMaxStages) return false; r[nst++] = 2; }
+  for (int i = 0; i < n3; ++i) { if (nst >= kMaxStages) return false; r[nst++] = 3; }
+  for (int i = 0; i < n5; ++i) { if (nst >= kMaxStages) return false; r[nst++] = 5; }
   p->n = n;
   p->nst = nst;
   p->min_radix = 8;
   for (int i = 0; i < nst; ++i) {
     p->radix[i] = r[i];
     if (r[i] < p->min_radix) p->min_radix = r[i];
+  }
+  // lines that one wavefront can carry through every stage with all of a
+  // lane's butterflies (at most kWaveRegs complex values) in registers
+  p->wave_lines = 0;
+  for (int l = 1; l <= 8; ++l) {
+    bool ok = true;
+    for (int i = 0; i < nst; ++i) {
+      const int per_lane = (l * (n / r[i]) + 63) / 64;
+      if (per_lane > kWaveRegs / r[i]) ok = false;
+    }
+    if (!ok) break;
+    p->wave_lines = l;
   }
   return true;
 }

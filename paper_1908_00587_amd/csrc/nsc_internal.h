@@ -18,12 +18,14 @@ constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 12;
 constexpr int kMaxFFT = 4096;
 constexpr int kFftThreads = 1024;  // launch bound of the FFT kernels
+constexpr int kWaveRegs = 16;      // complex values per lane in a wavefront-scope FFT stage
 constexpr int kNumStages = 11;  // timed kernels (see nsc_get_timings)
 
 struct FftPlan {
   int n = 0;
   int nst = 0;
   int min_radix = 8;
+  int wave_lines = 0;  // lines one wavefront transforms at once (0: block-scope only)
   int radix[kMaxStages] = {0};
 };
 
