@@ -70,6 +70,47 @@ def kernel_bytes(name, w, prec):
     return 0
 
 
+# device kernel behind each timed stage (mixed precision, the reported value)
+DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float>", "theta": "nsc::k_theta<float, true>",
+                 "zfwd": "nsc::k_zfwd<float>", "rhs": "nsc::k_rhs", "div": "nsc::k_div2",
+                 "sweep_pt": "nsc::k_sweep<true>", "sweep_vel": "nsc::k_sweep<true>",
+                 "finalize": "nsc::k_finalize", "influence": "nsc::k_influence"}
+
+
+def source_digest():
+    """SHA-256 over the HIP/C++ sources of the library (sorted by name): the
+    traffic counters of a committed profile apply only to the same kernels."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1908_00587_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(wname, stage):
+    """HBM bytes per launch of a stage's kernel from the committed counter
+    summary profiles/hbm-traffic_<workload>.txt (FETCH_SIZE + WRITE_SIZE,
+    each scaled by the calibration kernel's reading), or None when the file
+    is missing or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm-traffic_{wname}.txt")
+    if not os.path.exists(path) or stage not in DEVICE_KERNEL:
+        return None
+    digest, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] == "source_sha256":
+                digest = parts[1]
+            elif len(parts) >= 2 and parts[0] == "bytes_per_launch":
+                rows[" ".join(parts[2:])] = float(parts[1])
+    if digest != source_digest():
+        return None
+    return rows.get(DEVICE_KERNEL[stage])
+
+
 def calibration_copy():
     """A plain streaming kernel of known size (dst = -src: 256 MiB read,
     256 MiB written) after a 1 GiB fill that evicts the caches, so that the
@@ -217,10 +258,10 @@ def run_cpu(wname, steps):
                        f"{el:.1f} s")
 
 
-def pmc_summary(paths):
-    """Per-kernel average of each hardware counter over the dispatches of
-    rocprofv3 --pmc counter-collection CSV files (one line per kernel)."""
+def _pmc_means(paths):
+    """{kernel: {counter: mean over dispatches}} from rocprofv3 --pmc CSVs."""
     import csv
+    import re
     from collections import defaultdict
     acc = defaultdict(lambda: defaultdict(list))
     for path in paths:
@@ -233,23 +274,55 @@ def pmc_summary(paths):
                 if not short.startswith("nsc::"):
                     # library kernels (copies, fills) are told apart by their
                     # functor and size
-                    import re
                     fun = re.findall(r"at::native::(?:\(anonymous namespace\)::)?(\w+)", name)
                     tag = fun[1] if len(fun) > 1 else short
                     short = tag[:30] + " grid=" + row["Grid_Size"]
                 acc[short][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def traffic_report(wname, fetch_csv, write_csv):
+    """Text of profiles/hbm-traffic_<workload>.txt: per-launch HBM bytes of
+    every library kernel, FETCH_SIZE and WRITE_SIZE (KiB per dispatch) each
+    scaled by what the counter reads for the calibration kernel (256 MiB read
+    and written)."""
+    f = _pmc_means([fetch_csv])
+    w = _pmc_means([write_csv])
+    cal = max((k for k in f if not k.startswith("nsc::")), key=lambda k: f[k]["FETCH_SIZE"])
+    kib = 256 * 1024
+    ff = kib / f[cal]["FETCH_SIZE"]
+    fw = kib / w[cal]["WRITE_SIZE"]
+    out = [f"# HBM traffic per launch, workload {wname}",
+           f"# calibration kernel {cal}: FETCH_SIZE {f[cal]['FETCH_SIZE']:.1f} KiB, "
+           f"WRITE_SIZE {w[cal]['WRITE_SIZE']:.1f} KiB for {kib} KiB each "
+           f"-> factors {ff:.4f} (fetch), {fw:.4f} (write)",
+           f"source_sha256 {source_digest()}"]
+    for k in sorted(f):
+        if k.startswith("nsc::") and k in w:
+            b = 1024 * (ff * f[k]["FETCH_SIZE"] + fw * w[k]["WRITE_SIZE"])
+            out.append(f"fetch_write_kib {f[k]['FETCH_SIZE']:.1f} {w[k]['WRITE_SIZE']:.1f} {k}")
+            out.append(f"bytes_per_launch {b:.0f} {k}")
+    return "\n".join(out)
+
+
+def pmc_summary(paths):
+    """Per-kernel average of each hardware counter over the dispatches of
+    rocprofv3 --pmc counter-collection CSV files (one line per kernel)."""
+    acc = _pmc_means(paths)
     counters = sorted({c for k in acc.values() for c in k})
-    print("kernel".ljust(48) + "".join(c.rjust(14) for c in ["dispatches"] + counters))
+    width = [max(14, len(c) + 2) for c in counters]
+    print("kernel".ljust(48) + "".join(c.rjust(wd) for c, wd in zip(counters, width)))
     for k in sorted(acc):
-        n = max(len(v) for v in acc[k].values())
-        cells = [str(n)] + [f"{sum(acc[k][c]) / len(acc[k][c]):.6g}" if acc[k].get(c) else "-"
-                            for c in counters]
-        print(k[:48].ljust(48) + "".join(x.rjust(14) for x in cells))
+        cells = [f"{acc[k][c]:.6g}" if c in acc[k] else "-" for c in counters]
+        print(k[:48].ljust(48) + "".join(x.rjust(wd) for x, wd in zip(cells, width)))
 
 
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2:])
+        return
+    if len(sys.argv) == 5 and sys.argv[1] == "--traffic-report":
+        print(traffic_report(*sys.argv[2:]))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +369,8 @@ def main():
         "mixed_vs_fp64_rel_err": {k: float(f"{v:.3e}") for k, v in g["err"].items()},
         "roofline": {"bound": "hbm", "kernel": g["dominant"],
                      "achieved": round(g["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
+                     "traffic": committed_traffic(args.workload, g["dominant"]),
                      "bytes_per_launch": g["bytes"], "avg_launch_us": round(g["avg_us"], 3)},
         "adjoint_forward_cost_ratio": adj,
         "kernels": g["per_kernel"],

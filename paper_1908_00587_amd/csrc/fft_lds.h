@@ -1,6 +1,6 @@
 // LDS-resident mixed-radix FFTs for gfx950 (wave64).
 //
-// Lines of length n live in LDS with a padded stride.  Each stage is a
+// Lines of length n live in LDS, padded (one slot per 128 bytes).  Each stage is a
 // Stockham autosort pass (natural-order in, natural-order out): butterfly j
 // of a stage with accumulated length ns and radix R reads elements
 // j + r n/R, multiplies them by the twiddles w^{r (j mod ns)} with
@@ -20,6 +20,24 @@ template <typename T>
 struct alignas(2 * sizeof(T)) C2 {
   T x, y;
 };
+
+// Pointer into LDS (address space 3), so that out-of-line stage functions
+// still issue ds_read/ds_write rather than flat accesses.
+template <typename T>
+using LdsC2 = __attribute__((address_space(3))) C2<T> *;
+template <typename T>
+__device__ __forceinline__ LdsC2<T> to_lds(C2<T> *p) {
+  return (LdsC2<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ C2<T> lds_ld(LdsC2<T> p) {
+  return C2<T>{p->x, p->y};
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(LdsC2<T> p, C2<T> v) {
+  p->x = v.x;
+  p->y = v.y;
+}
 
 template <typename T>
 __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
@@ -125,6 +143,16 @@ struct Dft<T, 8, INV> {
   }
 };
 
+// LDS line layout: one padding slot after every 8 elements of a line, so that
+// the strided writes of the early Stockham stages (stride R elements) and the
+// transposed tile accesses spread over the LDS banks.
+template <typename T>
+__host__ __device__ constexpr int pad_shift() { return 3; }
+template <typename T>
+__device__ __forceinline__ int PD(int i) { return i + (i >> pad_shift<T>()); }
+template <typename T>
+__host__ __device__ constexpr int lds_line(int n) { return n + (n >> pad_shift<T>()) + 1; }
+
 // XCD-aware workgroup order: the dispatcher hands consecutive workgroups to
 // the 8 XCDs in turn, each with its own L2.  Remapping the linear workgroup
 // id gives every XCD a contiguous range of logical tiles, so neighbouring
@@ -153,21 +181,48 @@ __device__ __forceinline__ void load_twiddles(C2<T> *dst, const C2<T> *__restric
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
-// One Stockham stage over `nlines` lines (stride ls) of length n.
-// Requires nlines * n / R <= MAXB * blockDim.x.
-template <typename T, int R, bool INV, int MAXB>
-__device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
-                                          int ns, const C2<T> *tw) {
+// Wavefront-level ordering point: the LDS executes one wavefront's
+// instructions in program order, so only the compiler has to be kept from
+// moving LDS accesses across it or caching values over it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Affine addressing: with the pad period P (elements), the element offsets
+// j + r n/R of a butterfly's reads map to PD(j) + r (n/R)(1 + 1/P) when P
+// divides n/R, and its writes base + r ns to PD(base) + r ns (1 + 1/P) when
+// P divides ns, or to PD(base) + r when ns = 1 and R divides P.  The stage
+// then needs one add per access instead of a pad computation.
+template <typename T>
+__device__ __forceinline__ bool affine_stage(int n, int R, int ns) {
+  constexpr int P = 1 << pad_shift<T>();
+  const int nb = n / R;
+  return nb % P == 0 && (ns % P == 0 || (ns == 1 && P % R == 0));
+}
+
+// One Stockham stage over `nlines` lines (stride ls) of length n, executed
+// by `nthr` threads (tid = 0..nthr-1) that each hold MW butterflies in
+// registers between the read and the write phase.  BLOCK: the threads are
+// the workgroup (barriers); otherwise one wavefront (compiler fences only).
+// Requires nlines * n / R <= MW * nthr.
+template <typename T, int R, bool INV, int MW, bool BLOCK, bool AFF>
+__device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int ls, int ns,
+                                           LdsC2<T> tw, int tid, int nthr) {
+  constexpr int SH = pad_shift<T>();
   const int nb = n / R;
   const int total = nlines * nb;
   const int step = n / (ns * R);
   const bool pow2 = (ns & (ns - 1)) == 0;
   const float inb = 1.0f / (float)nb;
-  int jj[MAXB], ll[MAXB];
-  C2<T> v[MAXB][R];
+  const int nbp = nb + (nb >> SH);                 // padded read stride (AFF)
+  const int nsp = ns == 1 ? 1 : ns + (ns >> SH);   // padded write stride (AFF)
+  C2<T> v[MW][R];
+  int wl[MW], wa[MW];
 #pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + q * blockDim.x;
+  for (int q = 0; q < MW; ++q) {
+    const int b = tid + q * nthr;
     if (b < total) {
       int line = (int)(((float)b + 0.5f) * inb);
       int j = b - line * nb;
@@ -178,37 +233,62 @@ __device__ __forceinline__ void fft_stage(C2<T> *buf, int nlines, int n, int ls,
         ++line;
         j -= nb;
       }
-      jj[q] = j;
-      ll[q] = line;
       const int k = pow2 ? (j & (ns - 1)) : (j % ns);
-      const C2<T> *L = buf + line * ls;
+      LdsC2<T> L = buf + line * ls;
+      if (AFF) {
+        LdsC2<T> L0 = L + PD<T>(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = L[j + r * nb];
+        for (int r = 0; r < R; ++r) v[q][r] = lds_ld(L0 + r * nbp);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = lds_ld(L + PD<T>(j + r * nb));
+      }
       if (ns > 1) {  // the first stage has unit twiddles
+        const int ks = k * step;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C2<T> w = tw[r * k * step];
+          C2<T> w = lds_ld(tw + r * ks);
           if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
       }
       Dft<T, R, INV>::run(v[q]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + q * blockDim.x;
-    if (b < total) {
-      const int j = jj[q];
-      const int k = pow2 ? (j & (ns - 1)) : (j % ns);
-      C2<T> *L = buf + ll[q] * ls;
       const int base = (j - k) * R + k;  // (j / ns) ns R + j mod ns
-#pragma unroll
-      for (int r = 0; r < R; ++r) L[base + r * ns] = v[q][r];
+      wl[q] = line * ls;
+      wa[q] = AFF ? PD<T>(base) : base;
     }
   }
-  __syncthreads();
+  if (BLOCK) __syncthreads();
+  else wave_sync();
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    if (tid + q * nthr < total) {
+      LdsC2<T> L = buf + wl[q];
+      if (AFF) {
+        LdsC2<T> W0 = L + wa[q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds_st(W0 + r * nsp, v[q][r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds_st(L + PD<T>(wa[q] + r * ns), v[q][r]);
+      }
+    }
+  }
+  if (BLOCK) __syncthreads();
+  else wave_sync();
+}
+
+// Block-scope stage: one butterfly per thread (out of line, so that the
+// callers' registers stay free).
+template <typename T, int R, bool INV, int MAXB>
+__device__ __attribute__((noinline)) void fft_stage(LdsC2<T> buf, int nlines, int n, int ls,
+                                                    int ns, LdsC2<T> tw) {
+  if (affine_stage<T>(n, R, ns))
+    stage_body<T, R, INV, MAXB, true, true>(buf, nlines, n, ls, ns, tw, (int)threadIdx.x,
+                                            (int)blockDim.x);
+  else
+    stage_body<T, R, INV, MAXB, true, false>(buf, nlines, n, ls, ns, tw, (int)threadIdx.x,
+                                             (int)blockDim.x);
 }
 
 // Full transform of `nlines` LDS lines; forward (e^{-}) or inverse (e^{+}),
@@ -221,18 +301,19 @@ __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
   const int n = plan.n;
   int gl = (MAXB * (int)blockDim.x * plan.min_radix) / n;
   if (gl < 1) gl = 1;
+  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
   for (int l0 = 0; l0 < nlines; l0 += gl) {
     const int nl = nlines - l0 < gl ? nlines - l0 : gl;
-    C2<T> *b0 = buf + l0 * ls;
+    LdsC2<T> b0 = to_lds(buf + l0 * ls);
     int ns = 1;
     for (int s = 0; s < plan.nst; ++s) {
       const int R = plan.radix[s];
       switch (R) {
-        case 2: fft_stage<T, 2, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
-        case 3: fft_stage<T, 3, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
-        case 4: fft_stage<T, 4, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
-        case 5: fft_stage<T, 5, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
-        default: fft_stage<T, 8, INV, MAXB>(b0, nl, n, ls, ns, tw); break;
+        case 2: fft_stage<T, 2, INV, MAXB>(b0, nl, n, ls, ns, twl); break;
+        case 3: fft_stage<T, 3, INV, MAXB>(b0, nl, n, ls, ns, twl); break;
+        case 4: fft_stage<T, 4, INV, MAXB>(b0, nl, n, ls, ns, twl); break;
+        case 5: fft_stage<T, 5, INV, MAXB>(b0, nl, n, ls, ns, twl); break;
+        default: fft_stage<T, 8, INV, MAXB>(b0, nl, n, ls, ns, twl); break;
       }
       ns *= R;
     }
@@ -246,64 +327,20 @@ __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
 // barrier keeps the reads of a stage ahead of its writes and stops values
 // from being held in registers across stages.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
-// One Stockham stage over `nlines` lines of one wavefront; every butterfly of
-// the lane is held in registers between the read and the write phase
-// (host guarantee: nlines * n / R <= 64 * (kWaveRegs / R)).
+// One stage over `nlines` lines of one wavefront; every butterfly of the
+// lane is held in registers between the read and the write phase
+// (host guarantee: nlines * n / R <= 64 * (kWaveRegs / R)).  Out of line:
+// inlined into the callers' stage loops, the per-radix index math gets
+// hoisted across stages and exhausts the registers.
 template <typename T, int R, bool INV>
-__device__ __attribute__((noinline)) void wave_stage(C2<T> *buf, int nlines, int n, int ls, int ns,
-                                           const C2<T> *tw, int lane) {
+__device__ __attribute__((noinline)) void wave_stage(LdsC2<T> buf, int nlines, int n, int ls,
+                                                     int ns, LdsC2<T> tw, int lane) {
   constexpr int MW = kWaveRegs / R;
-  const int nb = n / R;
-  const int total = nlines * nb;
-  const int step = n / (ns * R);
-  const bool pow2 = (ns & (ns - 1)) == 0;
-  const float inb = 1.0f / (float)nb;
-  C2<T> v[MW][R];
-  int wa[MW];
-#pragma unroll
-  for (int q = 0; q < MW; ++q) {
-    const int b = lane + 64 * q;
-    if (b < total) {
-      int line = (int)(((float)b + 0.5f) * inb);
-      int j = b - line * nb;
-      if (j < 0) {
-        --line;
-        j += nb;
-      } else if (j >= nb) {
-        ++line;
-        j -= nb;
-      }
-      const int k = pow2 ? (j & (ns - 1)) : (j % ns);
-      const C2<T> *L = buf + line * ls;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = L[j + r * nb];
-      if (ns > 1) {  // the first stage has unit twiddles
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C2<T> w = tw[r * k * step];
-          if (INV) w.y = -w.y;
-          v[q][r] = cmul(v[q][r], w);
-        }
-      }
-      Dft<T, R, INV>::run(v[q]);
-      wa[q] = line * ls + (j - k) * R + k;
-    }
-  }
-  wave_sync();
-#pragma unroll
-  for (int q = 0; q < MW; ++q) {
-    if (lane + 64 * q < total) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[wa[q] + r * ns] = v[q][r];
-    }
-  }
-  wave_sync();
+  if (affine_stage<T>(n, R, ns))
+    stage_body<T, R, INV, MW, false, true>(buf, nlines, n, ls, ns, tw, lane, 64);
+  else
+    stage_body<T, R, INV, MW, false, false>(buf, nlines, n, ls, ns, tw, lane, 64);
 }
 
 // Transform of `nlines` lines owned by one wavefront, in groups of
@@ -313,18 +350,20 @@ __device__ void fft_wave(C2<T> *buf, int nlines, int ls, const FftPlan &plan, co
                          int lane) {
   const int n = plan.n;
   const int gl = plan.wave_lines;
+  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
   for (int l0 = 0; l0 < nlines; l0 += gl) {
     const int nl = nlines - l0 < gl ? nlines - l0 : gl;
-    C2<T> *b0 = buf + l0 * ls;
+    LdsC2<T> b0 = to_lds(buf + l0 * ls);
     int ns = 1;
     for (int s = 0; s < plan.nst; ++s) {
       const int R = plan.radix[s];
+      const int ln = lane;
       switch (R) {
-        case 2: wave_stage<T, 2, INV>(b0, nl, n, ls, ns, tw, lane); break;
-        case 3: wave_stage<T, 3, INV>(b0, nl, n, ls, ns, tw, lane); break;
-        case 4: wave_stage<T, 4, INV>(b0, nl, n, ls, ns, tw, lane); break;
-        case 5: wave_stage<T, 5, INV>(b0, nl, n, ls, ns, tw, lane); break;
-        default: wave_stage<T, 8, INV>(b0, nl, n, ls, ns, tw, lane); break;
+        case 2: wave_stage<T, 2, INV>(b0, nl, n, ls, ns, twl, ln); break;
+        case 3: wave_stage<T, 3, INV>(b0, nl, n, ls, ns, twl, ln); break;
+        case 4: wave_stage<T, 4, INV>(b0, nl, n, ls, ns, twl, ln); break;
+        case 5: wave_stage<T, 5, INV>(b0, nl, n, ls, ns, twl, ln); break;
+        default: wave_stage<T, 8, INV>(b0, nl, n, ls, ns, twl, ln); break;
       }
       ns *= R;
     }

@@ -22,7 +22,28 @@
 namespace nsc {
 namespace {
 
-constexpr int kMaxB = 1;  // one butterfly per thread per stage: low register use, high occupancy
+constexpr int kMaxB = 1;
+constexpr int kThetaWaveThreads = 256;  // at most four line sets per workgroup  // one butterfly per thread per stage: low register use, high occupancy
+
+// Items (row, col) of a rows x cols index space taken by thread t of n in
+// row-major order (item t + i n), stepped without a division per item.
+struct Walk2 {
+  int r, c, dr, dc, cols;
+  __device__ __forceinline__ Walk2(int t, int n, int cols_) : cols(cols_) {
+    r = t / cols;
+    c = t - r * cols;
+    dr = n / cols;
+    dc = n - dr * cols;
+  }
+  __device__ __forceinline__ void next() {
+    r += dr;
+    c += dc;
+    if (c >= cols) {
+      c -= cols;
+      ++r;
+    }
+  }
+};
 
 // Field `f` of the derived set at (row j, mode m, kk): 0..2 u_r, u_theta,
 // u_z; 3..5 omega_r, omega_theta, omega_z; 6..8 grad T.  With drop_mean the
@@ -90,33 +111,30 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax;
-  const int ls = (nz + 1);
+  const int ls = lds_line<T>(nz);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
   // retained modes: one item per (line, k) so that every thread's loads are
   // independent and issued together; then the zero padding
   const int mz = d.mz;
-  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
-    const int li = idx / mz;
-    const int kk = idx - li * mz;
+  for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
+    const int li = w.r;
+    const int kk = w.c;
     const int k = kk - K;
     const double2 v = derived(d, g, u, f, j, mt0 + li, kk, drop_mean != 0);
-    buf[li * ls + (k >= 0 ? k : nz + k)] = {T(v.x), T(v.y)};
+    buf[li * ls + PD<T>((k >= 0 ? k : nz + k))] = {T(v.x), T(v.y)};
   }
   const int npad = nz - mz;
-  for (int idx = threadIdx.x; idx < nl * npad; idx += blockDim.x) {
-    const int li = idx / npad;
-    const int b = K + 1 + (idx - li * npad);
-    buf[li * ls + b] = {T(0), T(0)};
-  }
+  for (Walk2 w(threadIdx.x, blockDim.x, npad); w.r < nl; w.next())
+    buf[w.r * ls + PD<T>(K + 1 + w.c)] = {T(0), T(0)};
   __syncthreads();
   fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = Z + ((size_t)f * d.nr + j) * nz * d.mt;
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int b = idx / nl;
-    const int li = idx - b * nl;
-    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + b];
+  for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
+    const int b = w.r;
+    const int li = w.c;
+    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + PD<T>(b)];
   }
 }
 
@@ -127,9 +145,9 @@ template <typename T>
 __device__ __forceinline__ void pack_pairs(C2<T> *buf, int ls, const C2<T> *__restrict__ zl,
                                            size_t fstride, int nf, int np, int nt, int mt,
                                            int gt, int gsz) {
-  for (int idx = gt; idx < np * mt; idx += gsz) {
-    const int p = idx / mt;
-    const int m = idx - p * mt;
+  for (Walk2 w(gt, gsz, mt); w.r < np; w.next()) {
+    const int p = w.r;
+    const int m = w.c;
     const int f1 = 2 * p, f2 = 2 * p + 1;
     const C2<T> F1 = zl[f1 * fstride + m];
     const C2<T> F2 = f2 < nf ? zl[f2 * fstride + m] : C2<T>{T(0), T(0)};
@@ -137,15 +155,13 @@ __device__ __forceinline__ void pack_pairs(C2<T> *buf, int ls, const C2<T> *__re
     if (m == 0) {
       L[0] = {F1.x, F2.x};
     } else {
-      L[m] = {F1.x - F2.y, F1.y + F2.x};
-      L[nt - m] = {F1.x + F2.y, F2.x - F1.y};
+      L[PD<T>(m)] = {F1.x - F2.y, F1.y + F2.x};
+      L[PD<T>(nt - m)] = {F1.x + F2.y, F2.x - F1.y};
     }
   }
   const int nzero = nt - 2 * mt + 1;
-  for (int idx = gt; idx < np * nzero; idx += gsz) {
-    const int p = idx / nzero;
-    buf[p * ls + mt + (idx - p * nzero)] = {T(0), T(0)};
-  }
+  for (Walk2 w(gt, gsz, nzero); w.r < np; w.next())
+    buf[w.r * ls + PD<T>(mt + w.c)] = {T(0), T(0)};
 }
 
 // Work group of the theta pass: with WAVE one wavefront per (r, z) line set
@@ -189,7 +205,8 @@ __device__ __forceinline__ void group_fft(C2<T> *buf, int nl, int ls, const FftP
 }
 
 template <typename T, bool WAVE>
-__global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
+__global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
+k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
                         C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
                         double dth, double dzs, double *__restrict__ cfl_part,
                         int want_cfl, const double *__restrict__ mean) {
@@ -197,7 +214,7 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
   __shared__ double red[3 * (kFftThreads / 64)];
   const int nt = d.nt, mt = d.mt;
-  const int ls = (nt + 1);
+  const int ls = lds_line<T>(nt);
   const int npi = (n_in + 1) / 2;
   const ThetaGroup grp = theta_group<WAVE>();
   const int gt = grp.gt, gsz = grp.gsz;
@@ -225,7 +242,8 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
   bool bad = false;
   const bool heated = n_in > 6;
   for (int a = gt; a < nt; a += gsz) {
-    C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
+    const int pa = PD<T>(a);
+    C2<T> l0 = buf[pa], l1 = buf[ls + pa], l2 = buf[2 * ls + pa];
     const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
     // u' x omega' + U x omega' + u' x Omega (Omega_r = 0); U x Omega is exact
     // in mode (0,0)
@@ -235,12 +253,12 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
     T ntt = T(0);
     if (heated) {
       // -(u' . grad T' + U . grad T' + u_r' dT_m/dr); -U_r dT_m/dr in mode (0,0)
-      C2<T> l3 = buf[3 * ls + a], l4 = buf[4 * ls + a];
+      C2<T> l3 = buf[3 * ls + pa], l4 = buf[4 * ls + pa];
       ntt = -((ur * l3.x + ut * l3.y + uz * l4.x) + (mU * l3.x + mV * l3.y + mW * l4.x) +
               ur * mG);
     }
-    buf[a] = {nr_, nth};
-    buf[ls + a] = {nzz, ntt};
+    buf[pa] = {nr_, nth};
+    buf[ls + pa] = {nzz, ntt};
     if (want_cfl) {
       const double aur = fabs((double)ur + mur), aut = fabs((double)ut + mut),
                    auz = fabs((double)uz + muz);
@@ -255,11 +273,11 @@ __global__ void __launch_bounds__(kFftThreads) k_theta(Dims d, Grid g, FftPlan p
   // unpack the two real transforms of each line, keep m < M_theta
   const int nout = heated ? 4 : 3;
   C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
-  for (int idx = gt; idx < 2 * mt; idx += gsz) {
-    const int p = idx / mt;
-    const int m = idx - p * mt;
-    const C2<T> zm = buf[p * ls + m];
-    const C2<T> zc = buf[p * ls + (m == 0 ? 0 : nt - m)];
+  for (Walk2 w(gt, gsz, mt); w.r < 2; w.next()) {
+    const int p = w.r;
+    const int m = w.c;
+    const C2<T> zm = buf[p * ls + PD<T>(m)];
+    const C2<T> zc = buf[p * ls + PD<T>(m == 0 ? 0 : nt - m)];
     // X = (Z_m + conj Z_{-m}) / 2, Y = (Z_m - conj Z_{-m}) / (2 i)
     const C2<T> x = {T(0.5) * (zm.x + zc.x), T(0.5) * (zm.y - zc.y)};
     const C2<T> y = {T(0.5) * (zm.y + zc.y), T(0.5) * (zc.x - zm.x)};
@@ -367,31 +385,31 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = (nz + 1);
+  const int ls = lds_line<T>(nz);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
   const C2<T> *in = W + ((size_t)f * d.nr + j) * nz * d.mt;
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int b = idx / nl;
-    const int li = idx - b * nl;
-    buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
+  for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
+    const int b = w.r;
+    const int li = w.c;
+    buf[li * ls + PD<T>(b)] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
   fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
-  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
-    const int li = idx / mz;
-    const int kk = idx - li * mz;
+  for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
+    const int li = w.r;
+    const int kk = w.c;
     const int m = mt0 + li;
     const int k = kk - K;
-    const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
+    const C2<T> v = buf[li * ls + PD<T>((k >= 0 ? k : nz + k))];
     const double2 bt = spectral_terms(d, u, mean, f, j, m, kk);
     double2 o = {(double)v.x * scale + bt.x, (double)v.y * scale + bt.y};
     const size_t md = (size_t)m * mz + kk;
     if (m == 0) {
       const int kkm = mz - 1 - kk;
-      const C2<T> vm = buf[li * ls + (k <= 0 ? -k : nz - k)];
+      const C2<T> vm = buf[li * ls + PD<T>((k <= 0 ? -k : nz - k))];
       const double2 bm = spectral_terms(d, u, mean, f, j, m, kkm);
       const double2 om = {(double)vm.x * scale + bm.x, (double)vm.y * scale + bm.y};
       o = {0.5 * (o.x + om.x), 0.5 * (o.y - om.y)};
@@ -441,15 +459,15 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = (nz + 1);
+  const int ls = lds_line<T>(nz);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
   const size_t plane = (size_t)d.nmodes;
   const double2 *src = nb + ((size_t)f * d.nr + j) * plane;
-  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
-    const int li = idx / mz;
-    const int kk = idx - li * mz;
+  for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
+    const int li = w.r;
+    const int kk = w.c;
     const int k = kk - K;
     const int m = mt0 + li;
     double2 v = src[(size_t)m * mz + kk];
@@ -458,33 +476,31 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
       v = make_double2(0.5 * (v.x + w.x), 0.5 * (v.y - w.y));
     }
     const double s = (m == 0 ? 1.0 : 0.5) * scale;
-    buf[li * ls + (k >= 0 ? k : nz + k)] = {T(v.x * s), T(v.y * s)};
+    buf[li * ls + PD<T>((k >= 0 ? k : nz + k))] = {T(v.x * s), T(v.y * s)};
   }
   const int npad = nz - mz;
-  for (int idx = threadIdx.x; idx < nl * npad; idx += blockDim.x) {
-    const int li = idx / npad;
-    buf[li * ls + K + 1 + (idx - li * npad)] = {T(0), T(0)};
-  }
+  for (Walk2 w(threadIdx.x, blockDim.x, npad); w.r < nl; w.next())
+    buf[w.r * ls + PD<T>(K + 1 + w.c)] = {T(0), T(0)};
   __syncthreads();
   fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
   C2<T> *out = W + ((size_t)f * d.nr + j) * nz * d.mt;
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int b = idx / nl;
-    const int li = idx - b * nl;
-    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + b];
+  for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
+    const int b = w.r;
+    const int li = w.c;
+    out[(size_t)b * d.mt + mt0 + li] = buf[li * ls + PD<T>(b)];
   }
 }
 
 // Per (r, z) line: forward fields from Z, adjoint outputs from W; pointwise
 // adjoint products; forward theta FFT of the input adjoints back into Z.
 template <typename T, bool WAVE>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
 k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
             const C2<T> *__restrict__ tw, int n_in, int n_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
   const int nt = d.nt, mt = d.mt;
-  const int ls = (nt + 1);
+  const int ls = lds_line<T>(nt);
   const int npi = (n_in + 1) / 2;
   const ThetaGroup grp = theta_group<WAVE>();
   const int gt = grp.gt, gsz = grp.gsz;
@@ -502,8 +518,9 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
   group_fft<T, WAVE, true>(buf, npi + 2, ls, pt, tws, gt);
   const bool heated = n_in > 6;
   for (int a = gt; a < nt; a += gsz) {
-    const C2<T> l0 = buf[a], l1 = buf[ls + a], l2 = buf[2 * ls + a];
-    const C2<T> n0 = buf[npi * ls + a], n1 = buf[(npi + 1) * ls + a];
+    const int pa = PD<T>(a);
+    const C2<T> l0 = buf[pa], l1 = buf[ls + pa], l2 = buf[2 * ls + pa];
+    const C2<T> n0 = buf[npi * ls + pa], n1 = buf[(npi + 1) * ls + pa];
     const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
     const T nr_ = n0.x, nth = n0.y, nzz = n1.x, ntt = n1.y;
     T bur = wt * nzz - wz * nth;
@@ -513,24 +530,24 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
     const T bwt = nzz * ur - nr_ * uz;
     const T bwz = nr_ * ut - nth * ur;
     if (heated) {
-      const C2<T> l3 = buf[3 * ls + a], l4 = buf[4 * ls + a];
+      const C2<T> l3 = buf[3 * ls + pa], l4 = buf[4 * ls + pa];
       bur -= ntt * l3.x;
       but -= ntt * l3.y;
       buz -= ntt * l4.x;
-      buf[3 * ls + a] = {-ntt * ur, -ntt * ut};
-      buf[4 * ls + a] = {-ntt * uz, T(0)};
+      buf[3 * ls + pa] = {-ntt * ur, -ntt * ut};
+      buf[4 * ls + pa] = {-ntt * uz, T(0)};
     }
-    buf[a] = {bur, but};
-    buf[ls + a] = {buz, bwr};
-    buf[2 * ls + a] = {bwt, bwz};
+    buf[pa] = {bur, but};
+    buf[ls + pa] = {buz, bwr};
+    buf[2 * ls + pa] = {bwt, bwz};
   }
   group_sync<WAVE>();
   group_fft<T, WAVE, false>(buf, npi, ls, pt, tws, gt);
-  for (int idx = gt; idx < npi * mt; idx += gsz) {
-    const int p = idx / mt;
-    const int m = idx - p * mt;
-    const C2<T> zm = buf[p * ls + m];
-    const C2<T> zc = buf[p * ls + (m == 0 ? 0 : nt - m)];
+  for (Walk2 w(gt, gsz, mt); w.r < npi; w.next()) {
+    const int p = w.r;
+    const int m = w.c;
+    const C2<T> zm = buf[p * ls + PD<T>(m)];
+    const C2<T> zc = buf[p * ls + PD<T>(m == 0 ? 0 : nt - m)];
     const C2<T> x = {T(0.5) * (zm.x + zc.x), T(0.5) * (zm.y - zc.y)};
     const C2<T> y = {T(0.5) * (zm.y + zc.y), T(0.5) * (zc.x - zm.x)};
     zl[(size_t)(2 * p) * fstride + m] = x;
@@ -549,25 +566,25 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
-  const int ls = (nz + 1);
+  const int ls = lds_line<T>(nz);
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
   const C2<T> *in = Z + ((size_t)f * d.nr + j) * nz * d.mt;
-  for (int idx = threadIdx.x; idx < nl * nz; idx += blockDim.x) {
-    const int b = idx / nl;
-    const int li = idx - b * nl;
-    buf[li * ls + b] = in[(size_t)b * d.mt + mt0 + li];
+  for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
+    const int b = w.r;
+    const int li = w.c;
+    buf[li * ls + PD<T>(b)] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
   fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
-  for (int idx = threadIdx.x; idx < nl * mz; idx += blockDim.x) {
-    const int li = idx / mz;
-    const int kk = idx - li * mz;
+  for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
+    const int li = w.r;
+    const int kk = w.c;
     const int m = mt0 + li;
     const int k = kk - K;
-    const C2<T> v = buf[li * ls + (k >= 0 ? k : nz + k)];
+    const C2<T> v = buf[li * ls + PD<T>((k >= 0 ? k : nz + k))];
     const double cm = m == 0 ? 1.0 : 2.0;
     double2 o = make_double2(cm * (double)v.x, cm * (double)v.y);
     db[((size_t)f * d.nr + j) * plane + (size_t)m * mz + kk] = o;
@@ -634,6 +651,9 @@ __global__ void k_derived_adj(Dims d, Grid g, const double2 *__restrict__ db,
 
 int min_radix(const FftPlan &p) { return p.min_radix; }
 
+// Padded LDS line length for element size esize (bytes of one complex value).
+int line_len(int n, size_t esize) { return esize == 8 ? lds_line<float>(n) : lds_line<double>(n); }
+
 // Threads so that nlines * n / min_radix butterflies fit kMaxB per thread,
 // capped at the FFT kernels' launch bound (then lines go in groups).
 int block_for(const FftPlan &p, int nlines, int floor_threads) {
@@ -648,7 +668,7 @@ int block_for(const FftPlan &p, int nlines, int floor_threads) {
 // Lines per block for the z passes: LDS budget and butterfly budget.
 int z_lines(const nsc_ctx *c, size_t esize) {
   const size_t budget = (size_t)c->lds_max - (size_t)c->d.nz * esize;
-  int tm = (int)(budget / ((size_t)(c->d.nz + 1) * esize));
+  int tm = (int)(budget / ((size_t)line_len(c->d.nz, esize) * esize));
   // lines beyond one butterfly per thread are transformed in groups; the
   // width of the transposed accesses (tm consecutive theta modes) matters more
   if (tm > 16) tm = 16;
@@ -669,8 +689,9 @@ int z_threads(const FftPlan &p, int tm) {
   return block_for(p, tm, 256);
 }
 
-// Theta-pass launch shape: wavefront-scope sets when the plan allows it and
-// a set's lines fit a modest LDS share, else one set per workgroup.
+// Theta-pass launch shape: wavefront-scope sets when a wavefront can carry
+// at least two lines per stage and a set's lines fit a modest LDS share,
+// else one set per workgroup.
 struct ThetaLaunch {
   bool wave;
   int waves;      // sets per workgroup (wave mode)
@@ -681,10 +702,10 @@ struct ThetaLaunch {
 
 ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize) {
   ThetaLaunch L;
-  const size_t line = (size_t)(c->d.nt + 1) * esize;
+  const size_t line = (size_t)line_len(c->d.nt, esize) * esize;
   const size_t tws = (size_t)c->d.nt * esize;
   const int nsets = c->d.nz * c->d.nr;
-  L.wave = c->plan_t.wave_lines > 0 && (size_t)nlines * line <= 24 * 1024;
+  L.wave = c->plan_t.wave_lines >= 2 && (size_t)nlines * line <= 24 * 1024;
   if (L.wave) {
     int w = (int)(((size_t)c->lds_max - tws) / ((size_t)nlines * line));
     if (w > 4) w = 4;
@@ -707,7 +728,7 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const int threads = z_threads(c->plan_z, tm);
-  const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   hipLaunchKernelGGL(k_mean, dim3((c->d.nr + 63) / 64), dim3(64), 0, c->stream, c->d, c->g,
                      reinterpret_cast<const double2 *>(u), c->s_mean);
   hipLaunchKernelGGL(k_zinv<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
@@ -737,7 +758,7 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw)
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
   const int threads = z_threads(c->plan_z, tm);
-  const size_t shm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
   hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->g, c->plan_z,
                      reinterpret_cast<const C2<T> *>(c->wbuf),
@@ -752,7 +773,7 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
                               const T *twz, const T *twt) {
   const int tm = z_lines(c, sizeof(C2<T>));
   const int zthreads = z_threads(c->plan_z, tm);
-  const size_t zshm = ((size_t)tm * (c->d.nz + 1) + c->d.nz) * sizeof(C2<T>);
+  const size_t zshm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   // forward fields on the (r, theta-spectral, z-physical) grid
   hipLaunchKernelGGL(k_zinv<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads), zshm,
                      c->stream, c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),

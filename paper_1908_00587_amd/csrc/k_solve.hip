@@ -396,6 +396,8 @@ struct SweepArgs {
 };
 constexpr int kSweepLanes = 64;
 
+constexpr int kPf = 16;  // factor rows in flight per sweep
+
 template <bool USE_LDS>
 __global__ void __launch_bounds__(kSweepLanes)
 k_sweep(Dims d, SweepArgs a) {
@@ -438,34 +440,38 @@ k_sweep(Dims d, SweepArgs a) {
   // right side into the LDS column with all loads in flight together
 #pragma unroll 8
   for (int j = 0; j < n; ++j) C(j) = ld(b + (size_t)j * P);
-  // forward substitution over the bulk rows, factor rows prefetched 4 ahead
+  // forward substitution over the bulk rows, factor rows prefetched kPf
+  // ahead (one wavefront per workgroup: registers are plentiful, and the
+  // prefetch depth is what hides the memory latency of the factor stream)
   const int nm = n - 4;
   auto row = [&](int j, int sl) { return vals[((size_t)j * kSlots + sl) * nops]; };
-  double fa[4][4];
+  double fa[kPf][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < kPf; ++r) {
     const int jj = r < nm ? r : nm - 1;
 #pragma unroll
     for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
   }
   Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
-  for (int j0 = 0; j0 < nm; j0 += 4) {
+  for (int j0 = 0; j0 < nm; j0 += kPf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kPf; ++r) {
       const int j = j0 + r;
       if (j < nm) {
+        // oldest terms first: the newest value y1 enters last, so the
+        // row-to-row dependency is a single fused multiply-add
         Cd y = C(j);
-        y = y - fa[r][3] * y1;
-        y = y - fa[r][2] * y2;
-        y = y - fa[r][1] * y3;
         y = y - fa[r][0] * y4;
+        y = y - fa[r][1] * y3;
+        y = y - fa[r][2] * y2;
+        y = y - fa[r][3] * y1;
         y4 = y3;
         y3 = y2;
         y2 = y1;
         y1 = y;
         C(j) = y;
       }
-      const int jn = j + 4 < nm ? j + 4 : nm - 1;
+      const int jn = j + kPf < nm ? j + kPf : nm - 1;
 #pragma unroll
       for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
     }
@@ -478,25 +484,25 @@ k_sweep(Dims d, SweepArgs a) {
     for (int c = n - 9; c <= j - 5; ++c) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * C(c);
     C(j) = y;
   }
-  // back substitution over rows N-1..4, prefetched 4 ahead
-  double u[4][5];
+  // back substitution over rows N-1..4, prefetched kPf ahead
+  double u[kPf][5];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < kPf; ++r) {
     const int jj = n - 1 - r >= 4 ? n - 1 - r : 4;
 #pragma unroll
     for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
   }
   Cd x1{0, 0}, x2{0, 0}, x3{0, 0}, x4{0, 0};
-  for (int j0 = n - 1; j0 >= 4; j0 -= 4) {
+  for (int j0 = n - 1; j0 >= 4; j0 -= kPf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kPf; ++r) {
       const int j = j0 - r;
       if (j >= 4) {
         Cd xv = C(j);
-        xv = xv - u[r][1] * x1;
-        xv = xv - u[r][2] * x2;
-        xv = xv - u[r][3] * x3;
         xv = xv - u[r][4] * x4;
+        xv = xv - u[r][3] * x3;
+        xv = xv - u[r][2] * x2;
+        xv = xv - u[r][1] * x1;
         xv = u[r][0] * xv;
         x4 = x3;
         x3 = x2;
@@ -504,7 +510,7 @@ k_sweep(Dims d, SweepArgs a) {
         x1 = xv;
         C(j) = xv;
       }
-      const int jn = j - 4 >= 4 ? j - 4 : 4;
+      const int jn = j - kPf >= 4 ? j - kPf : 4;
 #pragma unroll
       for (int t = 0; t < 5; ++t) u[r][t] = row(jn, 4 + t);
     }

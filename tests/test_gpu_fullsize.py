@@ -1,0 +1,111 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (wavefront-scope 192- and 768-point transforms, 16-line z
+tiles, affine padded LDS addressing), against the FP64 oracle on sampled
+outputs it can compute one by one: radial rows of the nonlinear term (the
+transforms of a row are independent of the other rows) and single Fourier
+modes of the implicit stage (the radial systems of a mode are independent of
+the other modes).  The heated workload also takes one full step against the
+oracle's full step."""
+import sys
+
+import pytest
+import torch
+
+import oracle as O
+from paper_1908_00587_amd.workloads import amplitudes, params
+from synthetic import direction
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(name, prec="fp64"):
+    import paper_1908_00587_amd as nsc
+    ctx = nsc.Context(*params(name))
+    ctx.set_precision(prec)
+    return ctx
+
+
+def rel(a, b):
+    a = a.detach().cpu()
+    b = b.detach().cpu()
+    return float((a - b).abs().max() / b.abs().max())
+
+
+ROWS = {"tc-heated-n64": [0, 1, 9, 31, 54, 62, 63], "tc-turb-n128": [0, 5, 64, 127]}
+
+
+@pytest.mark.parametrize("name", list(ROWS))
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", 2e-6)])
+def test_nonlinear_full_size_sampled_rows(name, prec, tol):
+    _say("nonlinear full size", name, prec)
+    p = O.Params(*params(name))
+    u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 81)
+    rows = torch.tensor(ROWS[name])
+    ref, dt_rows = O.nonlinear_planes(p, u, rows)
+    ref = O.herm(p, ref)
+    ctx = _ctx(name, prec)
+    out, c = ctx.nonlinear(u.cuda(), cfl=True)
+    torch.cuda.synchronize()
+    got = out.cpu()[:, rows]
+    assert rel(got, ref) < tol
+    # the bound over all rows is at most the bound over the sampled rows (up
+    # to the rounding of the transformed velocities: FP32 in mixed precision)
+    c = float(c.cpu()[0])
+    assert 0.0 < c <= dt_rows * (1 + (1e-14 if prec == "fp64" else 1e-6))
+
+
+MODES = {"tc-heated-n64": [(0, 63), (0, 10), (0, 116), (1, 63), (1, 0), (17, 80), (63, 126)],
+         "tc-turb-n128": [(0, 255), (0, 3), (0, 507), (2, 255), (100, 400), (255, 0)]}
+
+
+@pytest.mark.parametrize("name", list(MODES))
+def test_radial_solve_full_size_sampled_modes(name):
+    _say("radial_solve full size", name)
+    p = O.Params(*params(name))
+    u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 82)
+    Nn = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 83)
+    Nq = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 84)
+    dt, c = 1e-4, 0.5
+    ctx = _ctx(name)
+    ctx.set_timestep(dt=dt, c=c)
+    out, pres = ctx.radial_solve(u.cuda(), Nn.cuda(), Nq.cuda(), pressure=True)
+    torch.cuda.synchronize()
+    out, pres = out.cpu(), pres.cpu()
+    m = torch.tensor([a for a, _ in MODES[name]])
+    kk = torch.tensor([b for _, b in MODES[name]])
+    # the m = 0 column is Hermitian-averaged with its mirror (0, -k)
+    mirror = torch.where(m == 0, p.M_z - 1 - kk, kk)
+    X, P = O.radial_solve_modes(p, m, kk, u[:, :, m, kk], Nn[:, :, m, kk], Nq[:, :, m, kk], dt, c)
+    Xm, Pm = O.radial_solve_modes(p, m, mirror, u[:, :, m, mirror], Nn[:, :, m, mirror],
+                                  Nq[:, :, m, mirror], dt, c)
+    zero = (m == 0)
+    X = torch.where(zero, 0.5 * (X + Xm.conj()), X)
+    P = torch.where(zero, 0.5 * (P + Pm.conj()), P)
+    assert rel(out[:, :, m, kk], X) < TOL64
+    assert rel(pres[:, m, kk], P) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("mixed", 1e-5)])
+def test_step_full_size_heated(prec, tol):
+    """One predictor--corrector step of the heated workload from its initial
+    state, the whole field against the oracle's step."""
+    name = "tc-heated-n64"
+    _say("step full size", name, prec)
+    p = O.Params(*params(name))
+    u0 = O.initial_state(p, amplitudes(name))
+    dt = 2e-4
+    ref, dtc = O.step(p, u0, dt)
+    ctx = _ctx(name, prec)
+    ctx.set_timestep(dt=dt)
+    u = u0.cuda()
+    ctx.step(u, dt)
+    torch.cuda.synchronize()
+    for f in range(p.F):
+        assert rel(u[f], ref[f]) < tol, f
