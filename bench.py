@@ -60,9 +60,12 @@ def kernel_bytes(name, w, prec):
             b += 2 * S + nops_m * w["N_r"] * fac_row
         return b
     nmodes = w["M_theta"] * w["M_z"]
+    if name == "vel_rhs":
+        # right sides f - grad p0 in place: read 3S + p0, write 3S
+        return 3 * S + S + 3 * S
     if name == "sweep_vel":
-        # right sides f - grad p0 in place (read 3S + p0, write 3S), then sweeps
-        return 3 * S + S + 3 * S + 3 * S + 3 * S + nops_v * w["N_r"] * fac_row
+        # three Helmholtz sweeps: read 3S, write 3S, velocity factors
+        return 3 * S + 3 * S + nops_v * w["N_r"] * fac_row
     if name == "influence":
         return 3 * 18 * nmodes * 16 + nops_m * 32 + nmodes * 32
     if name == "finalize":
@@ -70,11 +73,14 @@ def kernel_bytes(name, w, prec):
     return 0
 
 
-# device kernel behind each timed stage (mixed precision, the reported value)
-DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float>", "theta": "nsc::k_theta<float, true>",
-                 "zfwd": "nsc::k_zfwd<float>", "rhs": "nsc::k_rhs", "div": "nsc::k_div2",
-                 "sweep_pt": "nsc::k_sweep<true>", "sweep_vel": "nsc::k_sweep<true>",
-                 "finalize": "nsc::k_finalize", "influence": "nsc::k_influence"}
+# device kernel behind each timed stage of the default workload (mixed
+# precision, the reported value; 192-point transforms)
+DEVICE_KERNEL_WORKLOAD = "tc-heated-n64"
+DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float, 192>", "theta": "nsc::k_theta<float, true, 192>",
+                 "zfwd": "nsc::k_zfwd<float, 192>", "rhs": "nsc::k_rhs", "div": "nsc::k_div2",
+                 "sweep_pt": "nsc::k_sweep<true, 0>", "sweep_vel": "nsc::k_sweep<true, 1>",
+                 "vel_rhs": "nsc::k_vel_rhs", "finalize": "nsc::k_finalize",
+                 "influence": "nsc::k_influence"}
 
 
 def source_digest():
@@ -96,7 +102,7 @@ def committed_traffic(wname, stage):
     each scaled by the calibration kernel's reading), or None when the file
     is missing or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm-traffic_{wname}.txt")
-    if not os.path.exists(path) or stage not in DEVICE_KERNEL:
+    if wname != DEVICE_KERNEL_WORKLOAD or not os.path.exists(path) or stage not in DEVICE_KERNEL:
         return None
     digest, rows = None, {}
     with open(path) as fh:
@@ -305,6 +311,38 @@ def traffic_report(wname, fetch_csv, write_csv):
     return "\n".join(out)
 
 
+def trace_summary(stats_csv, trace_csv):
+    """Text summary of a rocprofv3 --kernel-trace --stats run: the per-kernel
+    statistics table, then the library kernels per launch configuration
+    (grid and workgroup), which separates the workloads and stages that
+    share a kernel."""
+    import csv
+    from collections import defaultdict
+    out = ["kernel statistics (rocprofv3 --stats)",
+           f"{'kernel':70s} {'calls':>7s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
+           f"{'total_ms':>9s} {'pct':>6s}"]
+    for r in csv.DictReader(open(stats_csv, newline="")):
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0]
+        name = name[5:] if name.startswith("void ") else name
+        out.append(f"{name[:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:9.2f} "
+                   f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
+                   f"{float(r['TotalDurationNs']) / 1e6:9.3f} {float(r['Percentage']):6.2f}")
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv, newline="")):
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+        name = name[5:] if name.startswith("void ") else name
+        if not name.startswith("nsc::"):
+            continue
+        grid = "x".join(r[f"Grid_Size_{a}"] for a in "XYZ")
+        wg = "x".join(r[f"Workgroup_Size_{a}"] for a in "XYZ")
+        acc[(name, grid, wg)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out += ["", "library kernels per launch configuration (kernel trace)",
+            f"{'kernel':40s} {'grid (threads)':>22s} {'workgroup':>12s} {'calls':>7s} {'avg_us':>9s}"]
+    for (name, grid, wg), v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"{name[:40]:40s} {grid:>22s} {wg:>12s} {len(v):7d} {sum(v) / len(v) / 1e3:9.2f}")
+    return "\n".join(out)
+
+
 def pmc_summary(paths):
     """Per-kernel average of each hardware counter over the dispatches of
     rocprofv3 --pmc counter-collection CSV files (one line per kernel)."""
@@ -320,6 +358,9 @@ def pmc_summary(paths):
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2:])
+        return
+    if len(sys.argv) == 4 and sys.argv[1] == "--trace-summary":
+        print(trace_summary(sys.argv[2], sys.argv[3]))
         return
     if len(sys.argv) == 5 and sys.argv[1] == "--traffic-report":
         print(traffic_report(*sys.argv[2:]))

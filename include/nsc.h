@@ -174,11 +174,12 @@ int nsc_energy_grad(nsc_ctx *ctx, const double *u_hat, double *g);
 int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
 
 /* Per-kernel device time accumulated since the last call, in ms (HOST array
- * of n doubles), one entry per kernel: [0] z-inverse (curl + inverse z FFT),
- * [1] theta FFTs + products, [2] forward z FFT, [3] CFL reduction,
- * [4] right sides, [5] Poisson right side, [6] pressure/temperature sweeps,
- * [7] velocity right sides and sweeps, [8] influence coefficients, [9] finalisation,
- * [10] factorisation; entries [11..21] the launch counts of the same
+ * of n doubles), one entry per kernel: [0] z-inverse (mean profiles, curl,
+ * inverse z FFT), [1] theta FFTs + products, [2] forward z FFT, [3] CFL
+ * reduction, [4] right sides, [5] Poisson right side (and temperature wall
+ * rows), [6] pressure/temperature sweeps, [7] velocity sweeps, [8] influence
+ * coefficients, [9] finalisation, [10] factorisation, [11] velocity right
+ * sides (f - grad p); entries [12..23] the launch counts of the same
  * kernels.  Counters are reset by the call.  Timing is enabled by
  * nsc_set_profiling(ctx, 1): each kernel is then bracketed by HIP events on
  * the context stream and the host waits for the second event. */

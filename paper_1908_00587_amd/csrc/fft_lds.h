@@ -207,7 +207,7 @@ __device__ __forceinline__ bool affine_stage(int n, int R, int ns) {
 // registers between the read and the write phase.  BLOCK: the threads are
 // the workgroup (barriers); otherwise one wavefront (compiler fences only).
 // Requires nlines * n / R <= MW * nthr.
-template <typename T, int R, bool INV, int MW, bool BLOCK, bool AFF>
+template <typename T, int R, bool INV, int MW, bool BLOCK, bool AFF, bool CT = false>
 __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int ls, int ns,
                                            LdsC2<T> tw, int tid, int nthr) {
   constexpr int SH = pad_shift<T>();
@@ -224,14 +224,20 @@ __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int 
   for (int q = 0; q < MW; ++q) {
     const int b = tid + q * nthr;
     if (b < total) {
-      int line = (int)(((float)b + 0.5f) * inb);
-      int j = b - line * nb;
-      if (j < 0) {
-        --line;
-        j += nb;
-      } else if (j >= nb) {
-        ++line;
-        j -= nb;
+      int line, j;
+      if (CT) {  // compile-time n: exact division by a constant
+        line = b / nb;
+        j = b - line * nb;
+      } else {
+        line = (int)(((float)b + 0.5f) * inb);
+        j = b - line * nb;
+        if (j < 0) {
+          --line;
+          j += nb;
+        } else if (j >= nb) {
+          ++line;
+          j -= nb;
+        }
       }
       const int k = pow2 ? (j & (ns - 1)) : (j % ns);
       LdsC2<T> L = buf + line * ls;
@@ -370,20 +376,100 @@ __device__ void fft_wave(C2<T> *buf, int nlines, int ls, const FftPlan &plan, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-length wavefront transforms.  For the transform lengths of the
+// configured grids the stage sequence, strides, padded line length and
+// affine-address choice are compile-time constants, so the index arithmetic
+// of the butterflies folds into immediates (instruction offsets, constant
+// divisors).  Same stages, same order and same arithmetic as fft_wave.
+// ---------------------------------------------------------------------------
+struct CtRadices {
+  int nst;
+  int r[kMaxStages];
+};
+
+// The planner's radix order (8s, a 4 when the power of two needs it, a 2,
+// then 3s, then 5s) as a compile-time function of n.
+constexpr CtRadices ct_radices(int n) {
+  CtRadices p{0, {}};
+  int rem = n, a = 0, n3 = 0, n5 = 0;
+  while (rem % 5 == 0) { rem /= 5; ++n5; }
+  while (rem % 3 == 0) { rem /= 3; ++n3; }
+  while (rem % 2 == 0) { rem /= 2; ++a; }
+  while (a >= 3 && a != 4) { p.r[p.nst++] = 8; a -= 3; }
+  while (a >= 2) { p.r[p.nst++] = 4; a -= 2; }
+  if (a == 1) p.r[p.nst++] = 2;
+  for (int i = 0; i < n3; ++i) p.r[p.nst++] = 3;
+  for (int i = 0; i < n5; ++i) p.r[p.nst++] = 5;
+  return p;
+}
+
+constexpr int ct_ns(int n, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= ct_radices(n).r[i];
+  return ns;
+}
+
+// Lines one wavefront carries through every stage (the planner's rule).
+constexpr int ct_wave_lines(int n) {
+  const CtRadices p = ct_radices(n);
+  int gl = 0;
+  for (int l = 1; l <= 8; ++l) {
+    bool ok = true;
+    for (int i = 0; i < p.nst; ++i)
+      if ((l * (n / p.r[i]) + 63) / 64 > kWaveRegs / p.r[i]) ok = false;
+    if (!ok) break;
+    gl = l;
+  }
+  return gl;
+}
+
+template <typename T, bool INV, int N, int S>
+__device__ __forceinline__ void ct_stages(LdsC2<T> b0, int nl, LdsC2<T> tw, int lane) {
+  constexpr CtRadices P = ct_radices(N);
+  if constexpr (S < P.nst) {
+    constexpr int R = P.r[S];
+    constexpr int NS = ct_ns(N, S);
+    constexpr int PP = 1 << pad_shift<T>();
+    constexpr bool AFF = (N / R) % PP == 0 && (NS % PP == 0 || (NS == 1 && PP % R == 0));
+    stage_body<T, R, INV, kWaveRegs / R, false, AFF, true>(b0, nl, N, lds_line<T>(N), NS, tw,
+                                                           lane, 64);
+    ct_stages<T, INV, N, S + 1>(b0, nl, tw, lane);
+  }
+}
+
+// fft_wave for the fixed length N (line stride lds_line<T>(N)).
+template <typename T, bool INV, int N>
+__device__ __forceinline__ void fft_wave_ct(C2<T> *buf, int nlines, const C2<T> *tw, int lane) {
+  constexpr int GL = ct_wave_lines(N);
+  static_assert(GL > 0, "length too long for a wavefront-scope transform");
+  constexpr int LS = lds_line<T>(N);
+  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
+  for (int l0 = 0; l0 < nlines; l0 += GL) {
+    const int nl = nlines - l0 < GL ? nlines - l0 : GL;
+    ct_stages<T, INV, N, 0>(to_lds(buf + l0 * LS), nl, twl, lane);
+  }
+}
+
 // The nl lines of a workgroup: with a wavefront-scope plan each wavefront
 // transforms a contiguous share of them and the workgroup meets once at the
 // end; otherwise the whole workgroup works on each group of lines together.
-template <typename T, bool INV, int MAXB>
+// NF > 0: the line length is the compile-time constant NF.
+template <typename T, bool INV, int MAXB, int NF = 0>
 __device__ __forceinline__ void fft_block(C2<T> *buf, int nl, int ls, const FftPlan &plan,
                                           const C2<T> *tw) {
-  if (plan.wave_lines > 0) {
+  if (NF > 0 || plan.wave_lines > 0) {  // (fixed lengths always fit a wavefront)
     const int nw = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
     const int per = (nl + nw - 1) / nw;
     const int l0 = w * per;
     const int cnt = nl - l0 < per ? nl - l0 : per;
-    if (cnt > 0) fft_wave<T, INV>(buf + l0 * ls, cnt, ls, plan, tw, (int)(threadIdx.x & 63));
+    const int lane = (int)(threadIdx.x & 63);
+    if (cnt > 0) {
+      if constexpr (NF > 0) fft_wave_ct<T, INV, NF>(buf + l0 * ls, cnt, tw, lane);
+      else fft_wave<T, INV>(buf + l0 * ls, cnt, ls, plan, tw, lane);
+    }
     __syncthreads();
-  } else {
+  } else if constexpr (NF == 0) {
     fft_lines<T, INV, MAXB>(buf, nl, ls, plan, tw);
   }
 }

@@ -16,6 +16,7 @@
 // output stay FP64.
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "fft_lds.h"
 
@@ -102,9 +103,35 @@ __device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
   }
 }
 
-template <typename T>
+// Mean-flow profiles of mode (0,0) at radial row j (real parts, as carried
+// by the physical field) and their discrete derivatives: mean[.][j] = U_r,
+// V, W, T_m, Om_theta = -D1 W, Om_z = D1 V + V/r, G = D1 T_m.
+__device__ void mean_row(const Dims &d, const Grid &g, const double2 *__restrict__ u,
+                         double *__restrict__ mean, int j) {
+  const int n = d.nr;
+  const size_t P = d.nmodes;
+  auto M = [&](int f, int row) { return u[((size_t)f * n + row) * P + d.kmax].x; };
+  const int s = g.s[j];
+  const double *w = g.d1 + j * kStencil;
+  double dv = 0.0, dw = 0.0, dt = 0.0;
+  for (int t = 0; t < kStencil; ++t) {
+    dv = fma(w[t], M(1, s + t), dv);
+    dw = fma(w[t], M(2, s + t), dw);
+    if (d.heated) dt = fma(w[t], M(3, s + t), dt);
+  }
+  mean[j] = M(0, j);
+  mean[n + j] = M(1, j);
+  mean[2 * n + j] = M(2, j);
+  mean[3 * n + j] = d.heated ? M(3, j) : 0.0;
+  mean[4 * n + j] = -dw;
+  mean[5 * n + j] = dv + M(1, j) * g.rinv[j];
+  mean[6 * n + j] = dt;
+}
+
+template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
-                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm, int drop_mean) {
+                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm, int drop_mean,
+                       double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
   C2<T> *buf = tws + d.nz;
@@ -115,6 +142,8 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   const int mt0 = bx * tm;
   const int nl = min(tm, d.mt - mt0);
   load_twiddles(tws, tw, nz);
+  // one workgroup per radial row also records the mean-flow profiles there
+  if (bx == 0 && f == 0 && threadIdx.x == 0) mean_row(d, g, u, mean, j);
   // retained modes: one item per (line, k) so that every thread's loads are
   // independent and issued together; then the zero padding
   const int mz = d.mz;
@@ -129,7 +158,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   for (Walk2 w(threadIdx.x, blockDim.x, npad); w.r < nl; w.next())
     buf[w.r * ls + PD<T>(K + 1 + w.c)] = {T(0), T(0)};
   __syncthreads();
-  fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, true, kMaxB, NF>(buf, nl, ls, pz, tws);
   C2<T> *out = Z + ((size_t)f * d.nr + j) * nz * d.mt;
   for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
     const int b = w.r;
@@ -197,14 +226,15 @@ __device__ __forceinline__ void group_sync() {
   else __syncthreads();
 }
 
-template <typename T, bool WAVE, bool INV>
+template <typename T, bool WAVE, bool INV, int NF>
 __device__ __forceinline__ void group_fft(C2<T> *buf, int nl, int ls, const FftPlan &p,
                                           const C2<T> *tw, int gt) {
-  if (WAVE) fft_wave<T, INV>(buf, nl, ls, p, tw, gt);
+  if constexpr (WAVE && NF > 0) fft_wave_ct<T, INV, NF>(buf, nl, tw, gt);
+  else if constexpr (WAVE) fft_wave<T, INV>(buf, nl, ls, p, tw, gt);
   else fft_lines<T, INV, kMaxB>(buf, nl, ls, p, tw);
 }
 
-template <typename T, bool WAVE>
+template <typename T, bool WAVE, int NF>
 __global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
 k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
                         C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
@@ -229,7 +259,7 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
   // item per (pair, m) fills positions m and N_theta - m
   pack_pairs(buf, ls, zl, fstride, n_in, npi, nt, mt, gt, gsz);
   group_sync<WAVE>();
-  group_fft<T, WAVE, true>(buf, npi, ls, pt, tws, gt);
+  group_fft<T, WAVE, true, NF>(buf, npi, ls, pt, tws, gt);
   // pointwise products and CFL bound
   // CFL: the spacings are constant along the line set, so the smallest
   // Delta_i / |u_i| is Delta_i / max |u_i| (the same rounded value): the
@@ -269,7 +299,7 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
     }
   }
   group_sync<WAVE>();
-  group_fft<T, WAVE, false>(buf, 2, ls, pt, tws, gt);
+  group_fft<T, WAVE, false, NF>(buf, 2, ls, pt, tws, gt);
   // unpack the two real transforms of each line, keep m < M_theta
   const int nout = heated ? 4 : 3;
   C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
@@ -349,32 +379,7 @@ __device__ __forceinline__ double2 spectral_terms(const Dims &d, const double2 *
   return o;
 }
 
-// Mean-flow profiles of mode (0,0) per radial row (real parts, as carried
-// by the physical field) and their discrete derivatives.
-__global__ void k_mean(Dims d, Grid g, const double2 *__restrict__ u, double *__restrict__ mean) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = d.nr;
-  if (j >= n) return;
-  const size_t P = d.nmodes;
-  auto M = [&](int f, int row) { return u[((size_t)f * n + row) * P + d.kmax].x; };
-  const int s = g.s[j];
-  const double *w = g.d1 + j * kStencil;
-  double dv = 0.0, dw = 0.0, dt = 0.0;
-  for (int t = 0; t < kStencil; ++t) {
-    dv = fma(w[t], M(1, s + t), dv);
-    dw = fma(w[t], M(2, s + t), dw);
-    if (d.heated) dt = fma(w[t], M(3, s + t), dt);
-  }
-  mean[j] = M(0, j);
-  mean[n + j] = M(1, j);
-  mean[2 * n + j] = M(2, j);
-  mean[3 * n + j] = d.heated ? M(3, j) : 0.0;
-  mean[4 * n + j] = -dw;
-  mean[5 * n + j] = dv + M(1, j) * g.rinv[j];
-  mean[6 * n + j] = dt;
-}
-
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz, const C2<T> *__restrict__ W,
                        const double2 *__restrict__ u, double2 *__restrict__ nh,
                        const C2<T> *__restrict__ tw, int tm, double scale,
@@ -396,7 +401,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
     buf[li * ls + PD<T>(b)] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, false, kMaxB, NF>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
   for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
     const int li = w.r;
@@ -449,7 +454,7 @@ __global__ void k_cfl_final(const double *__restrict__ part, int n, double *out)
 // ---------------------------------------------------------------------------
 
 // Nbar (Hermitian-projected, divided by c_m and N_theta N_z) -> inverse z FFT.
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads)
 k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict__ W,
            const C2<T> *__restrict__ tw, int tm, double scale) {
@@ -482,7 +487,7 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
   for (Walk2 w(threadIdx.x, blockDim.x, npad); w.r < nl; w.next())
     buf[w.r * ls + PD<T>(K + 1 + w.c)] = {T(0), T(0)};
   __syncthreads();
-  fft_block<T, true, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, true, kMaxB, NF>(buf, nl, ls, pz, tws);
   C2<T> *out = W + ((size_t)f * d.nr + j) * nz * d.mt;
   for (Walk2 w(threadIdx.x, blockDim.x, nl); w.r < nz; w.next()) {
     const int b = w.r;
@@ -493,7 +498,7 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
 
 // Per (r, z) line: forward fields from Z, adjoint outputs from W; pointwise
 // adjoint products; forward theta FFT of the input adjoints back into Z.
-template <typename T, bool WAVE>
+template <typename T, bool WAVE, int NF>
 __global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
 k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
             const C2<T> *__restrict__ tw, int n_in, int n_out) {
@@ -515,7 +520,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
   pack_pairs(buf, ls, zl, fstride, n_in, npi, nt, mt, gt, gsz);
   pack_pairs(buf + npi * ls, ls, wl, fstride, n_out, 2, nt, mt, gt, gsz);
   group_sync<WAVE>();
-  group_fft<T, WAVE, true>(buf, npi + 2, ls, pt, tws, gt);
+  group_fft<T, WAVE, true, NF>(buf, npi + 2, ls, pt, tws, gt);
   const bool heated = n_in > 6;
   for (int a = gt; a < nt; a += gsz) {
     const int pa = PD<T>(a);
@@ -542,7 +547,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
     buf[2 * ls + pa] = {bwt, bwz};
   }
   group_sync<WAVE>();
-  group_fft<T, WAVE, false>(buf, npi, ls, pt, tws, gt);
+  group_fft<T, WAVE, false, NF>(buf, npi, ls, pt, tws, gt);
   for (Walk2 w(gt, gsz, mt); w.r < npi; w.next()) {
     const int p = w.r;
     const int m = w.c;
@@ -556,7 +561,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
 }
 
 // Forward z FFT of the input adjoints, times c_m -> Dbar[n_in][N_r][modes].
-template <typename T>
+template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads)
 k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict__ db,
            const C2<T> *__restrict__ tw, int tm) {
@@ -577,7 +582,7 @@ k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict_
     buf[li * ls + PD<T>(b)] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_block<T, false, kMaxB>(buf, nl, ls, pz, tws);
+  fft_block<T, false, kMaxB, NF>(buf, nl, ls, pz, tws);
   const size_t plane = (size_t)d.nmodes;
   for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
     const int li = w.r;
@@ -723,19 +728,36 @@ ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize) {
   return L;
 }
 
+// Transform lengths with compile-time kernels (the padded grids of the
+// configured workloads: 3 x 16, 32, 64 and 256 modes); others run the
+// runtime-length stages.  f receives std::integral_constant<int, NF>.
+template <class F>
+hipError_t with_fixed_len(int n, bool allow, F f) {
+  if (allow) {
+    switch (n) {
+      case 48: return f(std::integral_constant<int, 48>{});
+      case 96: return f(std::integral_constant<int, 96>{});
+      case 192: return f(std::integral_constant<int, 192>{});
+      case 768: return f(std::integral_constant<int, 768>{});
+      default: break;
+    }
+  }
+  return f(std::integral_constant<int, 0>{});
+}
+
 template <typename T>
 hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
-  hipLaunchKernelGGL(k_mean, dim3((c->d.nr + 63) / 64), dim3(64), 0, c->stream, c->d, c->g,
-                     reinterpret_cast<const double2 *>(u), c->s_mean);
-  hipLaunchKernelGGL(k_zinv<T>, grid, dim3(threads), shm, c->stream, c->d, c->g,
-                     c->plan_z, reinterpret_cast<const double2 *>(u),
-                     reinterpret_cast<C2<T> *>(c->zbuf),
-                     reinterpret_cast<const C2<T> *>(tw), tm, 1);
-  return hipGetLastError();
+  return with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+    hipLaunchKernelGGL((k_zinv<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
+                       c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
+                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(tw),
+                       tm, 1, c->s_mean);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -744,13 +766,16 @@ hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
   const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>));
   const double dth = 2.0 * M_PI / c->d.nt;
   const double dzs = c->d.lz / c->d.nz;
-  auto kern = L.wave ? k_theta<T, true> : k_theta<T, false>;
-  hipLaunchKernelGGL(kern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->g,
-                     c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
-                     reinterpret_cast<C2<T> *>(c->wbuf),
-                     reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
-                     c->cfl_part, want_cfl, c->s_mean);
-  return hipGetLastError();
+  return with_fixed_len(c->d.nt, L.wave, [&](auto nf) {
+    constexpr int NF = decltype(nf)::value;
+    auto kern = L.wave ? k_theta<T, true, NF> : k_theta<T, false, 0>;
+    hipLaunchKernelGGL(kern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->g,
+                       c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
+                       reinterpret_cast<C2<T> *>(c->wbuf),
+                       reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
+                       c->cfl_part, want_cfl, c->s_mean);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
@@ -760,11 +785,13 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw)
   const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
-  hipLaunchKernelGGL(k_zfwd<T>, grid, dim3(threads), shm, c->stream, c->d, c->g, c->plan_z,
-                     reinterpret_cast<const C2<T> *>(c->wbuf),
-                     reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
-                     reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean);
-  return hipGetLastError();
+  return with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+    hipLaunchKernelGGL((k_zfwd<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
+                       c->d, c->g, c->plan_z, reinterpret_cast<const C2<T> *>(c->wbuf),
+                       reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
+                       reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean);
+    return hipGetLastError();
+  });
 }
 
 
@@ -775,24 +802,42 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
   const int zthreads = z_threads(c->plan_z, tm);
   const size_t zshm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   // forward fields on the (r, theta-spectral, z-physical) grid
-  hipLaunchKernelGGL(k_zinv<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads), zshm,
-                     c->stream, c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
-                     reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz), tm, 0);
+  const dim3 gin((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
+  const dim3 gout((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
-  hipLaunchKernelGGL(k_zinv_adj<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out), dim3(zthreads),
-                     zshm, c->stream, c->d, c->plan_z, reinterpret_cast<const double2 *>(nbar),
-                     reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twz), tm,
-                     scale);
+  hipError_t e = with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+    constexpr int NF = decltype(nf)::value;
+    hipLaunchKernelGGL((k_zinv<T, NF>), gin, dim3(zthreads), zshm, c->stream, c->d, c->g,
+                       c->plan_z, reinterpret_cast<const double2 *>(u),
+                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz),
+                       tm, 0, c->s_mean);
+    hipLaunchKernelGGL((k_zinv_adj<T, NF>), gout, dim3(zthreads), zshm, c->stream, c->d,
+                       c->plan_z, reinterpret_cast<const double2 *>(nbar),
+                       reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twz),
+                       tm, scale);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
   const int npi = (c->n_in + 1) / 2;
   const ThetaLaunch L = theta_launch(c, npi + 2, sizeof(C2<T>));
-  auto tkern = L.wave ? k_theta_adj<T, true> : k_theta_adj<T, false>;
-  hipLaunchKernelGGL(tkern, L.grid, dim3(L.threads), L.shm, c->stream, c->d,
-                     c->plan_t, reinterpret_cast<C2<T> *>(c->zbuf),
-                     reinterpret_cast<const C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twt),
-                     c->n_in, c->n_out);
-  hipLaunchKernelGGL(k_zfwd_adj<T>, dim3((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in), dim3(zthreads),
-                     zshm, c->stream, c->d, c->plan_z, reinterpret_cast<const C2<T> *>(c->zbuf),
-                     reinterpret_cast<double2 *>(c->s_adj), reinterpret_cast<const C2<T> *>(twz), tm);
+  e = with_fixed_len(c->d.nt, L.wave, [&](auto nf) {
+    constexpr int NF = decltype(nf)::value;
+    auto tkern = L.wave ? k_theta_adj<T, true, NF> : k_theta_adj<T, false, 0>;
+    hipLaunchKernelGGL(tkern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->plan_t,
+                       reinterpret_cast<C2<T> *>(c->zbuf),
+                       reinterpret_cast<const C2<T> *>(c->wbuf),
+                       reinterpret_cast<const C2<T> *>(twt), c->n_in, c->n_out);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  e = with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+    hipLaunchKernelGGL((k_zfwd_adj<T, decltype(nf)::value>), gin, dim3(zthreads), zshm,
+                       c->stream, c->d, c->plan_z, reinterpret_cast<const C2<T> *>(c->zbuf),
+                       reinterpret_cast<double2 *>(c->s_adj),
+                       reinterpret_cast<const C2<T> *>(twz), tm);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_derived_adj, dim3((c->d.nmodes + 255) / 256, c->d.nr), dim3(256), 0, c->stream,
                      c->d, c->g, reinterpret_cast<const double2 *>(c->s_adj),
                      reinterpret_cast<const double2 *>(nbar), reinterpret_cast<double2 *>(ubar));

@@ -13,6 +13,8 @@
 // are laid out so that a wavefront's lanes read consecutive addresses.
 #include <cfloat>
 
+#include <type_traits>
+
 #include "nsc_internal.h"
 
 namespace nsc {
@@ -398,7 +400,13 @@ constexpr int kSweepLanes = 64;
 
 constexpr int kPf = 16;  // factor rows in flight per sweep
 
-template <bool USE_LDS>
+// FAMILY only names the launch (0: pressure/temperature, 1: velocity), so
+// that profiles tell the two apart; the code is the same.
+// NR > 0: the number of radial points as a compile-time constant, so that
+// the row loops unroll completely and the memory-wait counters can track
+// each prefetched factor row individually (with a rolled loop the waits at
+// the loop head drain every outstanding load).
+template <bool USE_LDS, int FAMILY, int NR>
 __global__ void __launch_bounds__(kSweepLanes)
 k_sweep(Dims d, SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -408,7 +416,9 @@ k_sweep(Dims d, SweepArgs a) {
   if (md >= d.nmodes) return;
   const SweepSys &S = a.s[blockIdx.y];
   const size_t P = d.nmodes;
-  const int n = d.nr;
+  const int n = NR > 0 ? NR : d.nr;
+  constexpr int kUnrollCol = NR > 0 ? NR : 8;   // column copies
+  constexpr int kUnrollRows = NR > 0 ? NR : 1;  // row groups of the sweeps
   const int kp1 = d.kmax + 1;
   const int m = md / d.mz;
   const int kk = md - m * d.mz;
@@ -438,7 +448,7 @@ k_sweep(Dims d, SweepArgs a) {
   const double *__restrict__ edge = F.edge + op;
   auto C = [&](int j) -> Cd & { return col[j * kSweepLanes + lane]; };
   // right side into the LDS column with all loads in flight together
-#pragma unroll 8
+#pragma unroll kUnrollCol
   for (int j = 0; j < n; ++j) C(j) = ld(b + (size_t)j * P);
   // forward substitution over the bulk rows, factor rows prefetched kPf
   // ahead (one wavefront per workgroup: registers are plentiful, and the
@@ -453,6 +463,7 @@ k_sweep(Dims d, SweepArgs a) {
     for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
   }
   Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
+#pragma unroll kUnrollRows
   for (int j0 = 0; j0 < nm; j0 += kPf) {
 #pragma unroll
     for (int r = 0; r < kPf; ++r) {
@@ -493,6 +504,7 @@ k_sweep(Dims d, SweepArgs a) {
     for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
   }
   Cd x1{0, 0}, x2{0, 0}, x3{0, 0}, x4{0, 0};
+#pragma unroll kUnrollRows
   for (int j0 = n - 1; j0 >= 4; j0 -= kPf) {
 #pragma unroll
     for (int r = 0; r < kPf; ++r) {
@@ -522,7 +534,7 @@ k_sweep(Dims d, SweepArgs a) {
     for (int c = j + 5; c <= 8; ++c) xv = xv - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * C(c);
     C(j) = row(j, 4) * xv;
   }
-#pragma unroll 8
+#pragma unroll kUnrollCol
   for (int j = 0; j < n; ++j) st(x + (size_t)j * P, C(j));
 }
 
@@ -570,14 +582,20 @@ __global__ void k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double
 
 // Poisson right side g = mask(div f); for mode (0,0) the mean-head right side
 // (D1 + 1/r) F_r inside, F_r(r_o) at the outer wall (zeros if not requested).
-__global__ void k_div2(Dims d, Grid g, const double2 *__restrict__ sf, double2 *__restrict__ sg,
+// Heated: the wall rows of f_T are replaced by the wall values (+-1/2 in
+// (0,0), zero elsewhere; all zero for walls = 0) in the same pass.
+__global__ void k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
                        const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc,
-                       int want_p) {
+                       int want_p, int walls) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
+  if (d.heated && (j == 0 || j == n - 1)) {
+    const bool mean = (md == d.kmax) && walls;
+    st(sf + ((size_t)3 * n + j) * P + md, Cd{mean ? (j == 0 ? 0.5 : -0.5) : 0.0, 0.0});
+  }
   if (md == d.kmax) {
     Cd r = {0, 0};
     if (want_p && nn && j > 0) {
@@ -609,16 +627,6 @@ __global__ void k_div2(Dims d, Grid g, const double2 *__restrict__ sf, double2 *
   const Cd vp = ld(fp + (size_t)j * P), vm = ld(fm + (size_t)j * P), vz = ld(fz + (size_t)j * P);
   st(sg + (size_t)j * P + md,
      0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz));
-}
-
-// Temperature wall rows of f_T replaced by the wall values (+-1/2 in (0,0)).
-__global__ void k_t_walls(Dims d, double2 *__restrict__ sfT, int walls) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  if (md >= d.nmodes) return;
-  const size_t P = d.nmodes;
-  const bool zero = (md == d.kmax) && walls;
-  st(sfT + md, Cd{zero ? 0.5 : 0.0, 0.0});
-  st(sfT + (size_t)(d.nr - 1) * P + md, Cd{zero ? -0.5 : 0.0, 0.0});
 }
 
 // lambda = -A^-1 beta(X0), beta = divergence at the two walls.
@@ -1254,7 +1262,7 @@ hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout) {
 }
 
 // stage 0: Poisson right side (+ temperature wall rows); 1: pressure and
-// temperature sweeps; 2: velocity right sides and sweeps.
+// temperature sweeps; 2: velocity right sides; 3: velocity sweeps.
 hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, const double *nq,
                                double cc, int walls, int want_p) {
   const Dims &d = c->d;
@@ -1266,33 +1274,35 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   const size_t col_bytes = (size_t)kSweepLanes * d.nr * sizeof(Cd);
   const bool lds = col_bytes <= 64 * 1024;
   const size_t shm = lds ? col_bytes : 0;
-  auto launch = [&](const SweepArgs &a, int nsys) {
+  auto launch = [&](const SweepArgs &a, int nsys, auto family) {
+    constexpr int FAM = decltype(family)::value;
     dim3 gr((d.nmodes + kSweepLanes - 1) / kSweepLanes, nsys);
-    if (lds)
-      hipLaunchKernelGGL(k_sweep<true>, gr, dim3(kSweepLanes), shm, c->stream, d, a);
+    if (lds && d.nr == 64)
+      hipLaunchKernelGGL((k_sweep<true, FAM, 64>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
+    else if (lds)
+      hipLaunchKernelGGL((k_sweep<true, FAM, 0>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
     else
-      hipLaunchKernelGGL(k_sweep<false>, gr, dim3(kSweepLanes), 0, c->stream, d, a);
+      hipLaunchKernelGGL((k_sweep<false, FAM, 0>), gr, dim3(kSweepLanes), 0, c->stream, d, a);
   };
   const size_t fld = (size_t)d.nr * d.nmodes;
   if (stage == 0) {
     hipLaunchKernelGGL(k_div2, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sg,
                        reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
-                       cc, wp);
-    if (d.heated)
-      hipLaunchKernelGGL(k_t_walls, mode_grid(c, 1), dim3(256), 0, c->stream, d, sf + 3 * fld, walls);
+                       cc, wp, walls);
   } else if (stage == 1) {
     // pressure (s_g -> s_p) and temperature (s_f[3] -> s_x[3]) in one launch
     SweepArgs a{};
     a.s[0] = SweepSys{c->fp, c->fp00, 0, wp ? 1 : 2, sg, sp};
     if (d.heated) a.s[1] = SweepSys{c->ft, c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
-    launch(a, d.heated ? 2 : 1);
-  } else {
+    launch(a, d.heated ? 2 : 1, std::integral_constant<int, 0>{});
+  } else if (stage == 2) {
     hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls);
+  } else {
     SweepArgs av{};
     av.s[0] = SweepSys{c->fv, c->fv, 1, 0, sf, sx};
     av.s[1] = SweepSys{c->fv, c->fv, 2, 0, sf + fld, sx + fld};
     av.s[2] = SweepSys{c->fv, c->fv, 0, 0, sf + 2 * fld, sx + 2 * fld};
-    launch(av, 3);
+    launch(av, 3, std::integral_constant<int, 1>{});
   }
   return hipGetLastError();
 }

@@ -240,8 +240,12 @@ int solve_impl(nsc_ctx *c, const double *un, const double *nn, const double *nq,
     HIPCHK(launch_solve_sweeps(c, 1, nn, nq, cc, walls, want_p));
   }
   {
-    StageTimer t(c, 7);
+    StageTimer t(c, 11);
     HIPCHK(launch_solve_sweeps(c, 2, nn, nq, cc, walls, want_p));
+  }
+  {
+    StageTimer t(c, 7);
+    HIPCHK(launch_solve_sweeps(c, 3, nn, nq, cc, walls, want_p));
   }
   {
     StageTimer t(c, 8);

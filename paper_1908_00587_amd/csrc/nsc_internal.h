@@ -19,7 +19,7 @@ constexpr int kMaxStages = 12;
 constexpr int kMaxFFT = 4096;
 constexpr int kFftThreads = 1024;  // launch bound of the FFT kernels
 constexpr int kWaveRegs = 16;      // complex values per lane in a wavefront-scope FFT stage
-constexpr int kNumStages = 11;  // timed kernels (see nsc_get_timings)
+constexpr int kNumStages = 12;  // timed kernels (see nsc_get_timings)
 
 struct FftPlan {
   int n = 0;
