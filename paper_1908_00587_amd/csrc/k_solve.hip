@@ -336,15 +336,14 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
   const double kap = (double)(kk - d.kmax) * d.kz;
   const double ri = g.rinv[j];
   const int s = g.s[j];
-  const double *w1 = g.d1 + j * kStencil;
-  const double *w2 = g.d2 + j * kStencil;
+  const double *lw = g.lw + j * kStencil;
   const double ce = 1.0 - cc;
   auto U = [&](int f, int row) { return ld(u + ((size_t)f * n + row) * P + md); };
   // stencil sums of (D2 + D1/r) applied to u_r, u_theta, u_z (and T)
   Cd lr = {0, 0}, lt = {0, 0}, lz = {0, 0}, lT = {0, 0};
 #pragma unroll
   for (int t = 0; t < kStencil; ++t) {
-    const double w = w2[t] + w1[t] * ri;
+    const double w = lw[t];
     lr = fmac(w, U(0, s + t), lr);
     lt = fmac(w, U(1, s + t), lt);
     lz = fmac(w, U(2, s + t), lz);
@@ -399,6 +398,8 @@ struct SweepArgs {
 constexpr int kSweepLanes = 64;
 
 constexpr int kPf = 16;  // factor rows in flight per sweep
+constexpr int kPc = 4;   // column entries read ahead per sweep (divides kPf)
+static_assert(kPf % kPc == 0, "the column ring follows the factor ring");
 
 // FAMILY only names the launch (0: pressure/temperature, 1: velocity), so
 // that profiles tell the two apart; the code is the same.
@@ -450,11 +451,28 @@ k_sweep(Dims d, SweepArgs a) {
   // right side into the LDS column with all loads in flight together
 #pragma unroll kUnrollCol
   for (int j = 0; j < n; ++j) C(j) = ld(b + (size_t)j * P);
-  // forward substitution over the bulk rows, factor rows prefetched kPf
-  // ahead (one wavefront per workgroup: registers are plentiful, and the
-  // prefetch depth is what hides the memory latency of the factor stream)
+  // Everything a row needs is requested well before the row: the factor
+  // rows kPf ahead (registers), the column entries kPc ahead (LDS reads),
+  // and the edge rows of both ends at the start.  One wavefront per
+  // workgroup: registers are plentiful, and the distance of these requests
+  // is what hides the memory latency of the recurrences.
   const int nm = n - 4;
   auto row = [&](int j, int sl) { return vals[((size_t)j * kSlots + sl) * nops]; };
+  // last four rows (forward) and first four rows (backward): band entries
+  // and the extra envelope entries
+  double lt[4][4], le[10], ut[4][5], ue[10];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) lt[r][t] = row(nm + r, t);
+#pragma unroll
+    for (int t = 0; t < 5; ++t) ut[r][t] = row(r, 4 + t);
+  }
+#pragma unroll
+  for (int e = 0; e < 10; ++e) {
+    le[e] = edge[(size_t)(10 + e) * nops];
+    ue[e] = edge[(size_t)e * nops];
+  }
   double fa[kPf][4];
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
@@ -462,6 +480,9 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
   }
+  Cd cb[kPc];
+#pragma unroll
+  for (int r = 0; r < kPc; ++r) cb[r] = C(r < nm ? r : nm - 1);
   Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
 #pragma unroll kUnrollRows
   for (int j0 = 0; j0 < nm; j0 += kPf) {
@@ -471,7 +492,7 @@ k_sweep(Dims d, SweepArgs a) {
       if (j < nm) {
         // oldest terms first: the newest value y1 enters last, so the
         // row-to-row dependency is a single fused multiply-add
-        Cd y = C(j);
+        Cd y = cb[r % kPc];  // = C(j): j0 is a multiple of kPf, kPc divides kPf
         y = y - fa[r][0] * y4;
         y = y - fa[r][1] * y3;
         y = y - fa[r][2] * y2;
@@ -481,21 +502,28 @@ k_sweep(Dims d, SweepArgs a) {
         y2 = y1;
         y1 = y;
         C(j) = y;
+        // row j + kPc has not been written yet (rows are written in order)
+        const int jc = j + kPc < nm ? j + kPc : nm - 1;
+        cb[r % kPc] = C(jc);
       }
       const int jn = j + kPf < nm ? j + kPf : nm - 1;
 #pragma unroll
       for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
     }
   }
-  for (int j = nm; j < n; ++j) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int j = nm + r;
     Cd y = C(j);
 #pragma unroll
-    for (int t = 1; t <= 4; ++t) y = y - row(j, 4 - t) * C(j - t);
+    for (int t = 1; t <= 4; ++t) y = y - lt[r][4 - t] * C(j - t);
     const int tt = n - 1 - j;
-    for (int c = n - 9; c <= j - 5; ++c) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * C(c);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c <= r) y = y - le[edge_off(tt) + c] * C(n - 9 + c);
     C(j) = y;
   }
-  // back substitution over rows N-1..4, prefetched kPf ahead
+  // back substitution over rows N-1..4
   double u[kPf][5];
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
@@ -503,6 +531,8 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
     for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
   }
+#pragma unroll
+  for (int r = 0; r < kPc; ++r) cb[r] = C(n - 1 - r >= 4 ? n - 1 - r : 4);
   Cd x1{0, 0}, x2{0, 0}, x3{0, 0}, x4{0, 0};
 #pragma unroll kUnrollRows
   for (int j0 = n - 1; j0 >= 4; j0 -= kPf) {
@@ -510,7 +540,8 @@ k_sweep(Dims d, SweepArgs a) {
     for (int r = 0; r < kPf; ++r) {
       const int j = j0 - r;
       if (j >= 4) {
-        Cd xv = C(j);
+        const int i = r % kPc;  // = (n - 1 - j) mod kPc
+        Cd xv = cb[i];
         xv = xv - u[r][4] * x4;
         xv = xv - u[r][3] * x3;
         xv = xv - u[r][2] * x2;
@@ -521,18 +552,24 @@ k_sweep(Dims d, SweepArgs a) {
         x2 = x1;
         x1 = xv;
         C(j) = xv;
+        // row j - kPc still holds the forward result (written downwards)
+        const int jc = j - kPc >= 4 ? j - kPc : 4;
+        cb[i] = C(jc);
       }
       const int jn = j - kPf >= 4 ? j - kPf : 4;
 #pragma unroll
       for (int t = 0; t < 5; ++t) u[r][t] = row(jn, 4 + t);
     }
   }
-  for (int j = 3; j >= 0; --j) {
-    Cd xv = C(j);
 #pragma unroll
-    for (int t = 1; t <= 4; ++t) xv = xv - row(j, 4 + t) * C(j + t);
-    for (int c = j + 5; c <= 8; ++c) xv = xv - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * C(c);
-    C(j) = row(j, 4) * xv;
+  for (int r = 3; r >= 0; --r) {
+    Cd xv = C(r);
+#pragma unroll
+    for (int t = 1; t <= 4; ++t) xv = xv - ut[r][t] * C(r + t);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < 4 - r) xv = xv - ue[edge_off(r) + c] * C(r + 5 + c);
+    C(r) = ut[r][0] * xv;
   }
 #pragma unroll kUnrollCol
   for (int j = 0; j < n; ++j) st(x + (size_t)j * P, C(j));

@@ -375,21 +375,27 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   }
   cc_weights_host(n, ccw.data());
   for (int j = 0; j < n; ++j) ccw[j] *= 0.5;
+  std::vector<double> lw(n * kStencil);
+  for (int j = 0; j < n; ++j)
+    for (int t = 0; t < kStencil; ++t)
+      lw[j * kStencil + t] = std::fma(d1[j * kStencil + t], rinv[j], d2[j * kStencil + t]);
   // device tables: one allocation
-  const size_t nd = (size_t)n * (1 + 1 + kStencil * 2 + 1 + 1);
+  const size_t nd = (size_t)n * (1 + 1 + kStencil * 3 + 1 + 1);
   TRY(dmalloc(&c->tables, nd * sizeof(double) + (size_t)n * sizeof(int) + 256));
   double *base = (double *)c->tables;
   double *p_r = base, *p_rinv = p_r + n, *p_d1 = p_rinv + n, *p_d2 = p_d1 + n * kStencil,
          *p_dr = p_d2 + n * kStencil, *p_cc = p_dr + n;
-  int *p_s = (int *)(p_cc + n);
+  double *p_lw = p_cc + n;
+  int *p_s = (int *)(p_lw + n * kStencil);
   HIPCHK(hipMemcpy(p_r, c->h_r, n * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_rinv, rinv.data(), n * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_d1, d1.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_d2, d2.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_dr, dr.data(), n * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_cc, ccw.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_lw, lw.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_s, s.data(), n * sizeof(int), hipMemcpyHostToDevice));
-  c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc};
+  c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc, p_lw};
 
   // twiddles
   {

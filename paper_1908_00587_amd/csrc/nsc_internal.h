@@ -38,6 +38,7 @@ struct Grid {
   const int *s;        // [N_r] first node of each row's window
   const double *dr;    // [N_r] local spacing for the CFL bound
   const double *ccw;   // [N_r] Clenshaw--Curtis weights on [r_i, r_o]
+  const double *lw;    // [N_r][9] weights of D2 + D1/r (fma(d1, 1/r, d2))
 };
 
 // Problem sizes and physical constants passed by value to kernels.
