@@ -323,11 +323,15 @@ __global__ void __launch_bounds__(64) k_influence_setup(Dims d, Grid g, Factors 
 }
 
 // f_X = X^n/dt + (1-c) L_q X^n + c N^q + (1-c) N^n for X in {+, -, z, T}.
+// blockIdx.z: 0 the +- pair (from u_r, u_theta), 1 u_z, 2 T -- one stencil
+// family per thread keeps the registers (and so the occupancy) of a
+// memory-bound kernel moderate.
 __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__restrict__ u,
                       const double2 *__restrict__ nn, const double2 *__restrict__ nq,
                       double2 *__restrict__ sf, double idt, double cc) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
+  const int part = blockIdx.z;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
@@ -338,42 +342,38 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
   const int s = g.s[j];
   const double *lw = g.lw + j * kStencil;
   const double ce = 1.0 - cc;
-  auto U = [&](int f, int row) { return ld(u + ((size_t)f * n + row) * P + md); };
-  // stencil sums of (D2 + D1/r) applied to u_r, u_theta, u_z (and T)
-  Cd lr = {0, 0}, lt = {0, 0}, lz = {0, 0}, lT = {0, 0};
-#pragma unroll
-  for (int t = 0; t < kStencil; ++t) {
-    const double w = lw[t];
-    lr = fmac(w, U(0, s + t), lr);
-    lt = fmac(w, U(1, s + t), lt);
-    lz = fmac(w, U(2, s + t), lz);
-    if (d.heated) lT = fmac(w, U(3, s + t), lT);
-  }
-  const Cd ur = U(0, j), ut = U(1, j), uz = U(2, j);
-  const Cd xp = ur + ci(ut), xm = ur - ci(ut);
-  const Cd lp = lr + ci(lt), lm = lr - ci(lt);
-  const double qp = (double)(m + 1), qm = (double)(m >= 1 ? m - 1 : 1 - m), qz = (double)m;
   const double k2 = kap * kap, r2 = ri * ri;
-  const Cd Lp = lp - (qp * qp * r2 + k2) * xp;
-  const Cd Lm = lm - (qm * qm * r2 + k2) * xm;
-  const Cd Lz = lz - (qz * qz * r2 + k2) * uz;
-  Cd np = {0, 0}, nmn = {0, 0}, nz = {0, 0}, nT = {0, 0};
-  if (nn) {
-    const Cd a = ld(nn + ((size_t)0 * n + j) * P + md), b = ld(nn + ((size_t)1 * n + j) * P + md);
-    const Cd a2 = ld(nq + ((size_t)0 * n + j) * P + md), b2 = ld(nq + ((size_t)1 * n + j) * P + md);
-    np = cc * (a2 + ci(b2)) + ce * (a + ci(b));
-    nmn = cc * (a2 - ci(b2)) + ce * (a - ci(b));
-    nz = cc * ld(nq + ((size_t)2 * n + j) * P + md) + ce * ld(nn + ((size_t)2 * n + j) * P + md);
-    if (d.heated)
-      nT = cc * ld(nq + ((size_t)3 * n + j) * P + md) + ce * ld(nn + ((size_t)3 * n + j) * P + md);
-  }
-  st(sf + ((size_t)0 * n + j) * P + md, idt * xp + ce * Lp + np);
-  st(sf + ((size_t)1 * n + j) * P + md, idt * xm + ce * Lm + nmn);
-  st(sf + ((size_t)2 * n + j) * P + md, idt * uz + ce * Lz + nz);
-  if (d.heated) {
-    const Cd T = U(3, j);
-    const Cd LT = lT - (qz * qz * r2 + k2) * T;
-    st(sf + ((size_t)3 * n + j) * P + md, idt * T + (ce / d.pr) * LT + nT);
+  auto U = [&](int f, int row) { return ld(u + ((size_t)f * n + row) * P + md); };
+  // stencil sum of (D2 + D1/r) applied to field f
+  auto L = [&](int f) {
+    Cd acc = {0, 0};
+#pragma unroll
+    for (int t = 0; t < kStencil; ++t) acc = fmac(lw[t], U(f, s + t), acc);
+    return acc;
+  };
+  auto N = [&](int f) -> Cd {
+    if (!nn) return Cd{0, 0};
+    const size_t o = ((size_t)f * n + j) * P + md;
+    return cc * ld(nq + o) + ce * ld(nn + o);
+  };
+  if (part == 0) {
+    const Cd lr = L(0), lt = L(1);
+    const Cd ur = U(0, j), ut = U(1, j);
+    const Cd xp = ur + ci(ut), xm = ur - ci(ut);
+    const Cd lp = lr + ci(lt), lm = lr - ci(lt);
+    const double qp = (double)(m + 1), qm = (double)(m >= 1 ? m - 1 : 1 - m);
+    const Cd Lp = lp - (qp * qp * r2 + k2) * xp;
+    const Cd Lm = lm - (qm * qm * r2 + k2) * xm;
+    const Cd a = N(0), b = N(1);
+    st(sf + ((size_t)0 * n + j) * P + md, idt * xp + ce * Lp + (a + ci(b)));
+    st(sf + ((size_t)1 * n + j) * P + md, idt * xm + ce * Lm + (a - ci(b)));
+  } else {
+    // u_z (operator L_m) or T (L_m / Pr)
+    const int f = part + 1;
+    const Cd x = U(f, j);
+    const Cd Lx = L(f) - ((double)m * (double)m * r2 + k2) * x;
+    const double cf = f == 3 ? ce / d.pr : ce;
+    st(sf + ((size_t)f * n + j) * P + md, idt * x + cf * Lx + N(f));
   }
 }
 
@@ -1228,7 +1228,8 @@ hipError_t launch_influence_setup(const nsc_ctx *c) {
 
 hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const double *nq,
                       double dt, double cc) {
-  hipLaunchKernelGGL(k_rhs, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+  hipLaunchKernelGGL(k_rhs, mode_grid(c, c->d.nr, c->d.heated ? 3 : 2), dim3(256), 0, c->stream,
+                     c->d, c->g,
                      reinterpret_cast<const double2 *>(u), reinterpret_cast<const double2 *>(nn),
                      reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_f),
                      1.0 / dt, cc);
