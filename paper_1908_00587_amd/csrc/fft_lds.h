@@ -175,6 +175,20 @@ __device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz) {
   bz = L / (gx * gy);
 }
 
+// As xcd_block, with z varying fastest in the logical order: the workgroups
+// of all fields of one (x, y) tile run next to each other on one XCD, so the
+// spectral rows they share are read from HBM once and then from its L2.
+__device__ __forceinline__ void xcd_block_zfirst(int &bx, int &by, int &bz) {
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int G = gx * gy * gz;
+  const int w = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int L = xcd_remap(w, G);
+  bz = L % gz;
+  const int rest = L / gz;
+  bx = rest % gx;
+  by = rest / gx;
+}
+
 // Copy the n twiddles of a plan into LDS (caller synchronises).
 template <typename T>
 __device__ __forceinline__ void load_twiddles(C2<T> *dst, const C2<T> *__restrict__ src, int n) {

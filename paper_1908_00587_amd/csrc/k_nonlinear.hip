@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
   C2<T> *buf = tws + d.nz;
   int bx, j, f;
-  xcd_block(bx, j, f);
+  xcd_block_zfirst(bx, j, f);  // the fields of one tile share their u rows
   const int nz = d.nz, K = d.kmax;
   const int ls = lds_line<T>(nz);
   const int mt0 = bx * tm;
