@@ -46,13 +46,24 @@ def energy_grad(ctx, u):
     return g
 
 
-def step_vjp(ctx, u, ubar_next, n_corr=1):
-    """Adjoint of one predictor--corrector step at state u (current dt):
-    recomputes the stage states, then walks the stages backwards."""
+def step_stages(ctx, u, n_corr=1):
+    """One predictor--corrector step at state u (current dt) by its stages:
+    returns (the stage states X^(1..n_corr) the adjoint needs, u^{n+1})."""
     a = ctx.nonlinear(u)
-    stages = [ctx.radial_solve(u, a, a)]
+    x = ctx.radial_solve(u, a, a)
+    stages = []
     for _ in range(n_corr):
-        stages.append(ctx.radial_solve(u, a, ctx.nonlinear(stages[-1])))
+        stages.append(x)
+        x = ctx.radial_solve(u, a, ctx.nonlinear(x))
+    return stages, x
+
+
+def step_vjp(ctx, u, ubar_next, n_corr=1, stages=None):
+    """Adjoint of one predictor--corrector step at state u (current dt),
+    walking the stages backwards; the stage states are recomputed unless
+    given (as returned by step_stages)."""
+    if stages is None:
+        stages, _ = step_stages(ctx, u, n_corr)
     ubar = torch.zeros_like(u)
     abar = torch.zeros_like(u)
     xbar = ubar_next
@@ -79,7 +90,9 @@ def rollout(ctx, u0, steps, dt):
 
 class RolloutEnergy(torch.autograd.Function):
     """E(u^S), u^{n+1} = Step(u^n), fixed dt; backward by checkpointing every
-    `ckpt_every` steps and recomputing each segment."""
+    `ckpt_every` steps and recomputing each segment once, stage by stage,
+    keeping its stage states for the vector--Jacobian products (memory: two
+    states per step of one segment for one corrector)."""
 
     @staticmethod
     def forward(fctx, u0, ctx, steps, dt, ckpt_every, n_corr):
@@ -107,13 +120,17 @@ class RolloutEnergy(torch.autograd.Function):
         for s in range(len(fctx.ckpts) - 1, -1, -1):
             n0 = s * C
             n1 = min(steps, n0 + C)
-            states = [fctx.ckpts[s].clone()]
-            for _ in range(n0, n1 - 1):
-                x = states[-1].clone()
-                ctx.step(x, fctx.dt)
+            # recompute the segment by stages, keeping each step's state and
+            # stage states (the same kernels in the same order as ctx.step)
+            states, stages = [], []
+            x = fctx.ckpts[s]
+            for _ in range(n0, n1):
                 states.append(x)
+                st, x = step_stages(ctx, x, fctx.n_corr)
+                stages.append(st)
             for k in range(n1 - n0 - 1, -1, -1):
-                ubar = step_vjp(ctx, states[k], ubar, fctx.n_corr)
+                ubar = step_vjp(ctx, states[k], ubar, fctx.n_corr, stages[k])
+                stages[k] = None
         return ubar, None, None, None, None, None
 
 
