@@ -166,6 +166,24 @@ int nsc_nonlinear_vjp(nsc_ctx *ctx, const double *u_hat, const double *n_bar,
 int nsc_radial_solve_vjp(nsc_ctx *ctx, const double *u_bar_out,
                          double *u_bar_n, double *n_bar_n, double *n_bar_q);
 
+/* One predictor--corrector step of the size set by nsc_set_timestep (fixed;
+ * no CFL bound, no step-size update) from u_hat, keeping the stage states the
+ * adjoint needs: stages = X^(1..n_corr) (n_corr consecutive state-sized
+ * arrays, written), u_next = u^{n+1} (written).  Same kernels and arithmetic
+ * as nsc_step, so the states agree with it bit for bit.  DEVICE arrays;
+ * u_next and stages must not alias u_hat or each other. */
+int nsc_step_stages(nsc_ctx *ctx, const double *u_hat, double *stages, double *u_next);
+
+/* Vector--Jacobian product of one step (the adjoint of nsc_step_stages at
+ * u_hat with its stage states): u_bar = (d u^{n+1} / d u^n)^T u_bar_next,
+ * written.  Chains the transposed stages: for q = n_corr..1 the transposed
+ * implicit stage, then the nonlinear VJP at X^(q); finally the predictor's
+ * transposed stage and the nonlinear VJP at u_hat.  DEVICE arrays; u_bar
+ * distinct from the inputs.  The first call allocates four state-sized
+ * adjoint workspaces (kept until nsc_destroy); NSC_ERR_OOM if that fails. */
+int nsc_step_vjp(nsc_ctx *ctx, const double *u_hat, const double *stages,
+                 const double *u_bar_next, double *u_bar);
+
 /* Gradient of nsc_energy: g = 2 pi L_z w_j r_j c_m (u - U_b) for the
  * velocity fields, 0 for T (c_0 = 1, c_m = 2).  g is written, not added. */
 int nsc_energy_grad(nsc_ctx *ctx, const double *u_hat, double *g);

@@ -3,7 +3,9 @@ kinetic energy after S steps with respect to the initial state
 (optimal-perturbation search), by checkpoint-and-recompute over steps.
 
 Every vector--Jacobian product runs in the library (nsc_nonlinear_vjp,
-nsc_radial_solve_vjp, nsc_energy_grad); this module only sequences them.
+nsc_radial_solve_vjp, nsc_energy_grad, and per step nsc_step_stages /
+nsc_step_vjp, which chain them in one call); this module only sequences
+them.
 The time-step schedule and the number of corrector stages are held fixed
 (not differentiated).  Inner product: sum over all stored entries of
 Re(conj(a) b), so a complex gradient entry is dE/dRe + i dE/dIm.
@@ -80,6 +82,26 @@ def step_vjp(ctx, u, ubar_next, n_corr=1, stages=None):
     return ubar
 
 
+def step_stages_fused(ctx, u, n_corr=1):
+    """step_stages in one library call (nsc_step_stages): returns
+    (stage states [n_corr][...], u^{n+1})."""
+    stages = torch.empty((max(n_corr, 1),) + tuple(u.shape), dtype=u.dtype, device=u.device)
+    u_next = torch.empty_like(u)
+    ctx._sync_stream()
+    check(ctx._L.nsc_step_stages(ctx._h, _p(u), _p(stages), _p(u_next)), "nsc_step_stages")
+    return stages, u_next
+
+
+def step_vjp_fused(ctx, u, stages, ubar_next):
+    """step_vjp in one library call (nsc_step_vjp) with the stage states of
+    step_stages_fused; returns ubar."""
+    ubar = torch.empty_like(u)
+    ctx._sync_stream()
+    check(ctx._L.nsc_step_vjp(ctx._h, _p(u), _p(stages), _p(ubar_next), _p(ubar)),
+          "nsc_step_vjp")
+    return ubar
+
+
 def rollout(ctx, u0, steps, dt):
     """Forward: `steps` steps of size dt from a copy of u0."""
     u = u0.clone()
@@ -126,10 +148,10 @@ class RolloutEnergy(torch.autograd.Function):
             x = fctx.ckpts[s]
             for _ in range(n0, n1):
                 states.append(x)
-                st, x = step_stages(ctx, x, fctx.n_corr)
+                st, x = step_stages_fused(ctx, x, fctx.n_corr)
                 stages.append(st)
             for k in range(n1 - n0 - 1, -1, -1):
-                ubar = step_vjp(ctx, states[k], ubar, fctx.n_corr, stages[k])
+                ubar = step_vjp_fused(ctx, states[k], stages[k], ubar)
                 stages[k] = None
         return ubar, None, None, None, None, None
 

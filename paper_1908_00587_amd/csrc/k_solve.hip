@@ -944,7 +944,12 @@ __global__ void k_adj_out(Dims d, const double2 *__restrict__ ub, double2 *__res
   const int n = d.nr;
   auto U = [&](int f, int m2) { return ld(ub + ((size_t)f * n + j) * P + m2); };
   Cd v[4];
-  for (int f = 0; f < d.f; ++f) {
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {  // (constant trip count: v stays in registers)
+    if (f >= d.f) {
+      v[f] = Cd{0, 0};
+      continue;
+    }
     v[f] = U(f, md);
     if (md < d.mz) {
       const Cd w = U(f, d.mz - 1 - md);
@@ -983,6 +988,7 @@ __global__ void k_adj_lambda(Dims d, Influence I, const double2 *__restrict__ sx
   const int op = m * kp1 + ka;
   const size_t ns = I.nops;
   Cd l1 = {0, 0}, l2 = {0, 0};
+#pragma unroll 8
   for (int j = 0; j < n; ++j) {
     const Cd xp = ld(sx + (size_t)j * P + md);
     const Cd xm = ld(sx + ((size_t)n + j) * P + md);
@@ -1065,6 +1071,222 @@ k_adj_vel(Dims d, Grid g, Factors fv, Factors ft, const double2 *__restrict__ sx
   lu_solve_t<Cd>(fv, q * kp1 + ka, n, rhs, outr);
   outr(0) = Cd{0, 0};
   outr(n - 1) = Cd{0, 0};
+}
+
+// ---------------------------------------------------------------------------
+// Transposed sweeps with the column in LDS (one lane per (mode, system), 64
+// lanes per workgroup): A^T x = b with A = LU, i.e. U^T y = b upwards, then
+// L^T x = y downwards, in place in the lane's LDS column.  The boundary rows
+// (0..8 and N-9..N-1, with the envelope entries) read their factors up
+// front; the bulk rows read theirs kPfT rows ahead.
+// ---------------------------------------------------------------------------
+constexpr int kPfT = 8;
+
+template <int NR, class COL>
+__device__ __forceinline__ void sweep_t_lds(const double *__restrict__ vals,
+                                            const double *__restrict__ edge, size_t nops, int nrt,
+                                            COL C) {
+  const int n = NR > 0 ? NR : nrt;
+  constexpr int kUnrollRows = NR > 0 ? NR : 1;
+  auto V = [&](int row, int slot) { return vals[((size_t)row * kSlots + slot) * nops]; };
+  // U^T y = b: rows 0..8 with the top envelope entries
+  {
+    double hu[9][5], he[10];
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+#pragma unroll
+      for (int t = 0; t < 5; ++t) hu[j][t] = V(j, 4 + t);  // U(j, j + t), t = 0 the inverse diagonal
+#pragma unroll
+    for (int e = 0; e < 10; ++e) he[e] = edge[(size_t)e * nops];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      Cd y = C(j);
+#pragma unroll
+      for (int t = 1; t <= 4; ++t)
+        if (j - t >= 0) y = y - hu[j - t][t] * C(j - t);
+#pragma unroll
+      for (int c = 0; c <= 3; ++c)
+        if (j - c >= 5) y = y - he[edge_off(c) + j - c - 5] * C(c);
+      C(j) = hu[j][0] * y;
+    }
+  }
+  {
+    // bulk rows 9..N-1: U(j-t, j) = slot 4 + t of row j - t, 1/U_jj = slot 4 of row j
+    double fa[kPfT][5];
+#pragma unroll
+    for (int r = 0; r < kPfT; ++r) {
+      const int j = 9 + r < n ? 9 + r : n - 1;
+#pragma unroll
+      for (int t = 1; t <= 4; ++t) fa[r][t] = V(j - t, 4 + t);
+      fa[r][0] = V(j, 4);
+    }
+    Cd y1 = C(8), y2 = C(7), y3 = C(6), y4 = C(5);
+#pragma unroll kUnrollRows
+    for (int j0 = 9; j0 < n; j0 += kPfT) {
+#pragma unroll
+      for (int r = 0; r < kPfT; ++r) {
+        const int j = j0 + r;
+        if (j < n) {
+          Cd y = C(j);
+          y = y - fa[r][4] * y4;
+          y = y - fa[r][3] * y3;
+          y = y - fa[r][2] * y2;
+          y = y - fa[r][1] * y1;
+          y = fa[r][0] * y;
+          y4 = y3;
+          y3 = y2;
+          y2 = y1;
+          y1 = y;
+          C(j) = y;
+        }
+        const int jn = j + kPfT < n ? j + kPfT : n - 1;
+#pragma unroll
+        for (int t = 1; t <= 4; ++t) fa[r][t] = V(jn - t, 4 + t);
+        fa[r][0] = V(jn, 4);
+      }
+    }
+  }
+  // L^T x = y: rows N-1..N-9 with the bottom envelope entries
+  {
+    double tl[9][5], te[10];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+      for (int t = 0; t < 5; ++t) tl[i][t] = V(n - 9 + i, t);  // L(row, row - 4 + t)
+#pragma unroll
+    for (int e = 0; e < 10; ++e) te[e] = edge[(size_t)(10 + e) * nops];
+#pragma unroll
+    for (int i = 8; i >= 0; --i) {
+      const int j = n - 9 + i;
+      Cd x = C(j);
+#pragma unroll
+      for (int t = 1; t <= 4; ++t)
+        if (i + t <= 8) x = x - tl[i + t][4 - t] * C(j + t);  // L(j + t, j)
+#pragma unroll
+      for (int ci = 5; ci <= 8; ++ci) {
+        const int c = n - 9 + ci;  // rows N-4..N-1
+        if (ci - i >= 5) x = x - te[edge_off(n - 1 - c) + j - (n - 9)] * C(c);
+      }
+      C(j) = x;
+    }
+  }
+  {
+    // bulk rows N-10..0: L(j + t, j) = slot 4 - t of row j + t
+    double fl[kPfT][5];
+#pragma unroll
+    for (int r = 0; r < kPfT; ++r) {
+      const int j = n - 10 - r >= 0 ? n - 10 - r : 0;
+#pragma unroll
+      for (int t = 1; t <= 4; ++t) fl[r][t] = V(j + t, 4 - t);
+    }
+    Cd x1 = C(n - 9), x2 = C(n - 8), x3 = C(n - 7), x4 = C(n - 6);
+#pragma unroll kUnrollRows
+    for (int j0 = n - 10; j0 >= 0; j0 -= kPfT) {
+#pragma unroll
+      for (int r = 0; r < kPfT; ++r) {
+        const int j = j0 - r;
+        if (j >= 0) {
+          Cd x = C(j);
+          x = x - fl[r][4] * x4;
+          x = x - fl[r][3] * x3;
+          x = x - fl[r][2] * x2;
+          x = x - fl[r][1] * x1;
+          x4 = x3;
+          x3 = x2;
+          x2 = x1;
+          x1 = x;
+          C(j) = x;
+        }
+        const int jn = j - kPfT >= 0 ? j - kPfT : 0;
+#pragma unroll
+        for (int t = 1; t <= 4; ++t) fl[r][t] = V(jn + t, 4 - t);
+      }
+    }
+  }
+}
+
+// k_adj_vel and k_adj_poisson with the LDS sweep: kind 0 the transposed
+// Helmholtz problems (blockIdx.y: 0/1/2 velocity +, -, z; 3 temperature),
+// kind 1 the transposed Poisson problem.  Same right sides and masks.
+template <int NR>
+__global__ void __launch_bounds__(kSweepLanes)
+k_adj_sweep(Dims d, Grid g, Factors fv, Factors ft, Factors fp, int kind,
+            const double2 *__restrict__ src, const double2 *__restrict__ bbar,
+            double2 *__restrict__ dst) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cd *col = reinterpret_cast<Cd *>(smem);
+  const int lane = threadIdx.x;
+  const int md = blockIdx.x * kSweepLanes + lane;
+  if (md >= d.nmodes) return;
+  const int comp = blockIdx.y;
+  const size_t P = d.nmodes;
+  const int n = NR > 0 ? NR : d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = md / d.mz;
+  const int kk = md - m * d.mz;
+  const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
+  const double kap = (double)(kk - d.kmax) * d.kz;
+  const bool zero = (m == 0 && ka == 0);
+  auto C = [&](int j) -> Cd & { return col[j * kSweepLanes + lane]; };
+  const double2 *xb = src + (size_t)(kind == 0 ? comp : 0) * n * P + md;
+  double2 *out = dst + (size_t)(kind == 0 ? comp : 0) * n * P + md;
+  Factors F = fv;
+  int op = 0;
+  if (kind == 1) {
+    if (zero) {
+      for (int j = 0; j < n; ++j) st(out + (size_t)j * P, Cd{0, 0});
+      return;
+    }
+    F = fp;
+    op = m * kp1 + ka;
+    for (int j = 0; j < n; ++j) C(j) = ld(xb + (size_t)j * P);
+  } else if (comp == 3) {
+    F = ft;
+    op = m * kp1 + ka;
+    for (int j = 0; j < n; ++j) C(j) = ld(xb + (size_t)j * P);
+  } else if (zero) {
+    if (comp == 1) return;
+    op = (comp == 0 ? 1 : 0) * kp1 + ka;
+    for (int j = 0; j < n; ++j) C(j) = ld(xb + (size_t)j * P);
+  } else {
+    const int q = comp == 0 ? m + 1 : (comp == 1 ? (m >= 1 ? m - 1 : 1 - m) : m);
+    op = q * kp1 + ka;
+    const Cd b0 = ld(bbar + 2 * (size_t)md), b1 = ld(bbar + 2 * (size_t)md + 1);
+    const double sgn = comp == 0 ? 1.0 : -1.0;
+    for (int j = 0; j < n; ++j) {
+      Cd v = ld(xb + (size_t)j * P);
+      if (comp < 2) {
+        // 1/2 (D1 + (1 +- m)/r)^T e_w beta_bar_w
+        if (j <= 8) {
+          double c = g.d1[0 * kStencil + j];
+          if (j == 0) c += (1.0 + sgn * m) * g.rinv[0];
+          v = v + (0.5 * c) * b0;
+        }
+        if (j >= n - 9) {
+          double c = g.d1[(n - 1) * kStencil + (j - g.s[n - 1])];
+          if (j == n - 1) c += (1.0 + sgn * m) * g.rinv[n - 1];
+          v = v + (0.5 * c) * b1;
+        }
+      } else {
+        if (j == 0) v = v - kap * ci(b0);
+        if (j == n - 1) v = v - kap * ci(b1);
+      }
+      C(j) = v;
+    }
+  }
+  sweep_t_lds<NR>(F.vals + op, F.edge + op, F.nops, n, C);
+  C(0) = Cd{0, 0};
+  C(n - 1) = Cd{0, 0};
+  if (kind == 0 && zero && comp == 0) {  // fbar+ = (i/2) rbar_theta, fbar- = -(i/2) rbar_theta
+    double2 *om = dst + (size_t)n * P + md;
+    for (int j = 0; j < n; ++j) {
+      const Cd h = 0.5 * ci(C(j));
+      st(out + (size_t)j * P, h);
+      st(om + (size_t)j * P, Cd{-h.x, -h.y});
+    }
+    return;
+  }
+  for (int j = 0; j < n; ++j) st(out + (size_t)j * P, C(j));
 }
 
 // pbar0 = -D1^T (rbar+ + rbar-) + (m/r)(rbar+ - rbar-) + i kappa rbar_z.
@@ -1154,7 +1376,12 @@ k_adj_in(Dims d, Grid g, const double2 *__restrict__ fb, double idt, double cc,
   const double ce = 1.0 - cc;
   Cd xb[4], fv[4];
   const int nf = d.heated ? 4 : 3;
-  for (int c = 0; c < nf; ++c) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {  // (constant trip count: xb, fv stay in registers)
+    if (c >= nf) {
+      xb[c] = fv[c] = Cd{0, 0};
+      continue;
+    }
     const double2 *f = fb + (size_t)c * n * P + md;
     const double q = c == 0 ? (double)(m + 1) : (c == 1 ? (double)(m >= 1 ? m - 1 : 1 - m) : (double)m);
     const Cd v = ld(f + (size_t)j * P);
@@ -1282,14 +1509,55 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
   double2 *lam = reinterpret_cast<double2 *>(c->s_lam);
   hipLaunchKernelGGL(k_adj_out, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, ub, sx);
   hipLaunchKernelGGL(k_adj_lambda, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->inf, sx, lam);
-  hipLaunchKernelGGL(k_adj_vel, mode_grid(c, c->d.heated ? 4 : 3), dim3(256), 0, c->stream, c->d, c->g,
-                     c->fv, c->ft, sx, lam, sf);
+  const size_t col_bytes = (size_t)kSweepLanes * c->d.nr * sizeof(Cd);
+  const bool lds = col_bytes <= 64 * 1024;
+  const dim3 lg((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, c->d.heated ? 4 : 3);
+  const dim3 lg1((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, 1);
+  if (lds && c->d.nr == 64)
+    hipLaunchKernelGGL(k_adj_sweep<64>, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+                       c->fv, c->ft, c->fp, 0, sx, lam, sf);
+  else if (lds)
+    hipLaunchKernelGGL(k_adj_sweep<0>, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+                       c->fv, c->ft, c->fp, 0, sx, lam, sf);
+  else
+    hipLaunchKernelGGL(k_adj_vel, mode_grid(c, c->d.heated ? 4 : 3), dim3(256), 0, c->stream, c->d,
+                       c->g, c->fv, c->ft, sx, lam, sf);
   hipLaunchKernelGGL(k_adj_pbar, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sp);
-  hipLaunchKernelGGL(k_adj_poisson, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->fp, sp, sg);
+  if (lds && c->d.nr == 64)
+    hipLaunchKernelGGL(k_adj_sweep<64>, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+                       c->fv, c->ft, c->fp, 1, sp, lam, sg);
+  else if (lds)
+    hipLaunchKernelGGL(k_adj_sweep<0>, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+                       c->fv, c->ft, c->fp, 1, sp, lam, sg);
+  else
+    hipLaunchKernelGGL(k_adj_poisson, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->fp, sp, sg);
   hipLaunchKernelGGL(k_adj_f, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sg, sx);
   hipLaunchKernelGGL(k_adj_in, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sx, 1.0 / dt,
                      cc, reinterpret_cast<double2 *>(ubar_n), reinterpret_cast<double2 *>(nbar_n),
                      reinterpret_cast<double2 *>(nbar_q));
+  return hipGetLastError();
+}
+
+__global__ void k_fill_zero(double *__restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void k_add(double *__restrict__ y, const double *__restrict__ x, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+// n doubles set to zero / y += x, in kernels (no memset node when captured)
+hipError_t launch_fill_zero(const nsc_ctx *c, double *p, size_t n) {
+  const size_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, c->stream, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const nsc_ctx *c, double *y, const double *x, size_t n) {
+  const size_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+  hipLaunchKernelGGL(k_add, dim3((unsigned)blocks), dim3(256), 0, c->stream, y, x, n);
   return hipGetLastError();
 }
 

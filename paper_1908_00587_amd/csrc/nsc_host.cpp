@@ -282,7 +282,7 @@ int nsc_destroy(nsc_ctx *c) {
   if (!c) return NSC_OK;
   void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
                   c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
-                  c->s_lam, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
+                  c->s_lam, c->s_vjp, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_factors(&c->fv);
@@ -581,6 +581,56 @@ int nsc_radial_solve_vjp(nsc_ctx *c, const double *ubar_out, double *ubar_n, dou
     return NSC_ERR_ARG;
   TRY(ensure_factors(c, c->dt, c->c));
   HIPCHK(launch_solve_vjp(c, ubar_out, ubar_n, nbar_n, nbar_q, c->dt, c->c));
+  return NSC_OK;
+}
+
+int nsc_step_stages(nsc_ctx *c, const double *u, double *stages, double *u_next) {
+  if (!c || !u || !stages || !u_next) return NSC_ERR_ARG;
+  const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;  // doubles per state
+  const int nc = c->n_corr;
+  if ((const void *)u_next == (const void *)u) return NSC_ERR_ARG;
+  if (nc > 0 && (u_next < stages + nc * fld && stages < u_next + fld)) return NSC_ERR_ARG;
+  if (nc > 0 && (u < stages + nc * fld && stages < u + fld)) return NSC_ERR_ARG;
+  double *xs = const_cast<double *>(u);
+  // same sequence as nsc_step: N(u); X^(1) = S(u, N, N); X^(q+1) = S(u, N, N(X^(q)))
+  TRY(nonlinear_impl(c, xs, c->s_nn, nullptr));
+  TRY(solve_impl(c, xs, c->s_nn, c->s_nn, nc == 0 ? u_next : stages, nullptr, c->dt, c->c, 1));
+  for (int q = 1; q <= nc; ++q) {
+    TRY(nonlinear_impl(c, stages + (size_t)(q - 1) * fld, c->s_nq, nullptr));
+    TRY(solve_impl(c, xs, c->s_nn, c->s_nq, q == nc ? u_next : stages + (size_t)q * fld, nullptr,
+                   c->dt, c->c, 1));
+  }
+  return NSC_OK;
+}
+
+int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double *ubar_next,
+                 double *ubar) {
+  if (!c || !u || !stages || !ubar_next || !ubar) return NSC_ERR_ARG;
+  if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)ubar_next)
+    return NSC_ERR_ARG;
+  const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
+  const int nc = c->n_corr;
+  if (ubar < stages + (size_t)nc * fld && stages < ubar + fld) return NSC_ERR_ARG;
+  if (!c->s_vjp) TRY(dmalloc((void **)&c->s_vjp, 4 * fld * sizeof(double)));
+  double *abar = c->s_vjp, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
+  TRY(ensure_factors(c, c->dt, c->c));
+  HIPCHK(launch_fill_zero(c, ubar, fld));
+  HIPCHK(launch_fill_zero(c, abar, fld));
+  const double *xbar = ubar_next;
+  for (int q = nc; q >= 1; --q) {
+    // X^(q+1) = S(u, a, N(X^(q)))
+    HIPCHK(launch_fill_zero(c, bbar, fld));
+    HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+    double *xn = (xbar == xa) ? xb : xa;
+    HIPCHK(launch_fill_zero(c, xn, fld));
+    HIPCHK(launch_nonlinear_vjp(c, c->precision, stages + (size_t)(q - 1) * fld, bbar, xn));
+    xbar = xn;
+  }
+  // X^(1) = S(u, a, a)
+  HIPCHK(launch_fill_zero(c, bbar, fld));
+  HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+  HIPCHK(launch_add(c, abar, bbar, fld));
+  HIPCHK(launch_nonlinear_vjp(c, c->precision, u, abar, ubar));
   return NSC_OK;
 }
 

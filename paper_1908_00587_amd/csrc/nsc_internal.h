@@ -103,6 +103,7 @@ struct nsc_ctx {
   double *s_p = nullptr;    // [N_r][modes] complex p0
   double *s_x = nullptr;    // [4][N_r][modes] complex X0+, X0-, X0z, T
   double *s_lam = nullptr;  // [modes][2] complex
+  double *s_vjp = nullptr;  // adjoint workspaces of nsc_step_vjp: 4 states (allocated on first use)
   double *s_u1 = nullptr;   // [F][N_r][modes] complex intermediate state
   double *s_nn = nullptr;   // [F][N_r][modes] complex N^n
   double *s_nq = nullptr;   // [F][N_r][modes] complex N^q
@@ -131,6 +132,8 @@ hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha,
 hipError_t launch_influence_setup(const nsc_ctx *c);
 hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn,
                       const double *nq, double dt, double cc);
+hipError_t launch_fill_zero(const nsc_ctx *c, double *p, size_t n);
+hipError_t launch_add(const nsc_ctx *c, double *y, const double *x, size_t n);
 hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, const double *nq,
                                double cc, int walls, int want_p);
 hipError_t launch_influence(const nsc_ctx *c);

@@ -138,3 +138,30 @@ def test_rollout_gradient_finite_differences_adjoint_workload():
         worst = max(worst, abs(fd - an) / abs(fd))
         _say(f"dir {s}: fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(fd):.2e}")
     assert worst <= 1e-6
+
+
+def test_fused_step_calls_match_composition():
+    """nsc_step_stages reproduces nsc_step bit for bit, and nsc_step_vjp the
+    Python composition of the stage VJPs (same kernels in the same order)."""
+    _say("fused step stages / vjp")
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import (step_stages, step_stages_fused, step_vjp,
+                                              step_vjp_fused)
+    args = CASES["heated"]
+    p = O.Params(*args)
+    ctx = nsc.Context(*args)
+    dt = 1e-3
+    ctx.set_timestep(dt=dt)
+    u = O.initial_state(p, mode_amplitudes(p.F, p.M_theta, p.M_z, 1e-3, seed=31)).cuda()
+    st, un = step_stages_fused(ctx, u)
+    ref = u.clone()
+    ctx.step(ref, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(un, ref)
+    st2, _ = step_stages(ctx, u)
+    assert torch.equal(st[0], st2[0])
+    ubar_next = direction(p.F, p.N_r, p.M_theta, p.M_z, 32).cuda()
+    a = step_vjp_fused(ctx, u, st, ubar_next)
+    b = step_vjp(ctx, u, ubar_next, 1, st2)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max() / b.abs().max()) < 1e-14
