@@ -968,34 +968,53 @@ __global__ void k_adj_out(Dims d, const double2 *__restrict__ ub, double2 *__res
 }
 
 // lambda_bar_j = sum_r (X_j+ Xbar+ + X_j- Xbar- + i kappa h_j Xbar_z);
-// beta_bar = -A^-T lambda_bar.
-__global__ void k_adj_lambda(Dims d, Influence I, const double2 *__restrict__ sx,
-                             double2 *__restrict__ bbar) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  if (md >= d.nmodes) return;
+// beta_bar = -A^-T lambda_bar.  Workgroup of 64 modes x 4 row quarters; the
+// quarters' partial sums meet in LDS (fixed order).
+constexpr int kLamModes = 64, kLamParts = 4;
+
+__global__ void __launch_bounds__(kLamModes * kLamParts)
+k_adj_lambda(Dims d, Influence I, const double2 *__restrict__ sx, double2 *__restrict__ bbar) {
+  __shared__ Cd part[kLamParts - 1][2][kLamModes];
+  const int lane = threadIdx.x % kLamModes, q = threadIdx.x / kLamModes;
+  const int md = blockIdx.x * kLamModes + lane;
+  const bool live = md < d.nmodes;
   const size_t P = d.nmodes;
   const int n = d.nr;
   const int kp1 = d.kmax + 1;
-  const int m = md / d.mz;
-  const int kk = md - m * d.mz;
+  const int m = live ? md / d.mz : 0;
+  const int kk = live ? md - m * d.mz : d.kmax;
   const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
-  if (m == 0 && ka == 0) {
-    st(bbar + 2 * (size_t)md, Cd{0, 0});
-    st(bbar + 2 * (size_t)md + 1, Cd{0, 0});
-    return;
-  }
   const double kap = (double)(kk - d.kmax) * d.kz;
   const int op = m * kp1 + ka;
   const size_t ns = I.nops;
   Cd l1 = {0, 0}, l2 = {0, 0};
-#pragma unroll 8
-  for (int j = 0; j < n; ++j) {
-    const Cd xp = ld(sx + (size_t)j * P + md);
-    const Cd xm = ld(sx + ((size_t)n + j) * P + md);
-    const Cd xz = kap * ci(ld(sx + ((size_t)2 * n + j) * P + md));  // i kappa Xbar_z
-    auto Rv = [&](int s) { return I.resp[((size_t)s * n + j) * ns + op]; };
-    l1 = l1 + (Rv(2) * xp + Rv(4) * xm + Rv(6) * xz);
-    l2 = l2 + (Rv(3) * xp + Rv(5) * xm + Rv(7) * xz);
+  const int j0 = (n * q) / kLamParts, j1 = (n * (q + 1)) / kLamParts;
+  if (live) {
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+      const Cd xp = ld(sx + (size_t)j * P + md);
+      const Cd xm = ld(sx + ((size_t)n + j) * P + md);
+      const Cd xz = kap * ci(ld(sx + ((size_t)2 * n + j) * P + md));  // i kappa Xbar_z
+      auto Rv = [&](int s) { return I.resp[((size_t)s * n + j) * ns + op]; };
+      l1 = l1 + (Rv(2) * xp + Rv(4) * xm + Rv(6) * xz);
+      l2 = l2 + (Rv(3) * xp + Rv(5) * xm + Rv(7) * xz);
+    }
+  }
+  if (q > 0) {
+    part[q - 1][0][lane] = l1;
+    part[q - 1][1][lane] = l2;
+  }
+  __syncthreads();
+  if (q != 0 || !live) return;
+#pragma unroll
+  for (int t = 0; t < kLamParts - 1; ++t) {
+    l1 = l1 + part[t][0][lane];
+    l2 = l2 + part[t][1][lane];
+  }
+  if (m == 0 && ka == 0) {
+    st(bbar + 2 * (size_t)md, Cd{0, 0});
+    st(bbar + 2 * (size_t)md + 1, Cd{0, 0});
+    return;
   }
   const double a00 = I.ainv[op], a01 = I.ainv[ns + op], a10 = I.ainv[2 * ns + op], a11 = I.ainv[3 * ns + op];
   st(bbar + 2 * (size_t)md, Cd{-(a00 * l1.x + a10 * l2.x), -(a00 * l1.y + a10 * l2.y)});
@@ -1508,7 +1527,8 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
   double2 *sp = reinterpret_cast<double2 *>(c->s_p);
   double2 *lam = reinterpret_cast<double2 *>(c->s_lam);
   hipLaunchKernelGGL(k_adj_out, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, ub, sx);
-  hipLaunchKernelGGL(k_adj_lambda, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->inf, sx, lam);
+  hipLaunchKernelGGL(k_adj_lambda, dim3((c->d.nmodes + kLamModes - 1) / kLamModes), dim3(kLamModes * kLamParts),
+                     0, c->stream, c->d, c->inf, sx, lam);
   const size_t col_bytes = (size_t)kSweepLanes * c->d.nr * sizeof(Cd);
   const bool lds = col_bytes <= 64 * 1024;
   const dim3 lg((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, c->d.heated ? 4 : 3);

@@ -615,14 +615,14 @@ int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double
   double *abar = c->s_vjp, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
   TRY(ensure_factors(c, c->dt, c->c));
   HIPCHK(launch_fill_zero(c, ubar, fld));
-  HIPCHK(launch_fill_zero(c, abar, fld));
+  HIPCHK(launch_fill_zero(c, c->s_vjp, 4 * fld));  // abar, bbar and both x buffers
   const double *xbar = ubar_next;
   for (int q = nc; q >= 1; --q) {
     // X^(q+1) = S(u, a, N(X^(q)))
-    HIPCHK(launch_fill_zero(c, bbar, fld));
+    if (q != nc) HIPCHK(launch_fill_zero(c, bbar, fld));
     HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
     double *xn = (xbar == xa) ? xb : xa;
-    HIPCHK(launch_fill_zero(c, xn, fld));
+    if (q != nc) HIPCHK(launch_fill_zero(c, xn, fld));
     HIPCHK(launch_nonlinear_vjp(c, c->precision, stages + (size_t)(q - 1) * fld, bbar, xn));
     xbar = xn;
   }
