@@ -90,10 +90,15 @@ constexpr int kBW = 17;  // band window width: columns i-8 .. i+8
 constexpr int kFacThreads = 32;
 
 // One thread per operator: op = q*(K+1) + |k|.  Band elimination without
-// pivoting over a sliding 9-row window held in LDS.
+// pivoting over a sliding 9-row window held in LDS.  blockIdx.y picks one of
+// two operator sets of the same kind and shift (velocity and temperature
+// Helmholtz operators differ only in beta): both factorise in one launch.
 __global__ void __launch_bounds__(kFacThreads)
-k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_off) {
+k_factor(Dims d, Grid g, Factors F0, Factors F1, int kind, double alpha, double beta0,
+         double beta1, int q_off) {
   __shared__ double win[9 * kBW * kFacThreads];
+  const Factors F = blockIdx.y == 0 ? F0 : F1;
+  const double beta = blockIdx.y == 0 ? beta0 : beta1;
   const int tid = threadIdx.x;
   const int op = blockIdx.x * kFacThreads + tid;
   if (op >= F.nops) return;
@@ -112,27 +117,60 @@ k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_o
     for (int e = 0; e < kEdge; ++e) F.edge[(size_t)e * nops + op] = 0.0;
     return;
   }
-  auto load_row = [&](int i) {
+  auto store_row = [&](int i, const double *a, int s) {
     const int ring = i % 9;
     for (int bi = 0; bi < kBW; ++bi) W(ring, bi) = 0.0;
-    double a[kStencil];
-    int s;
-    R.row(g, n, i, a, s);
     for (int t = 0; t < kStencil; ++t) W(ring, s + t - i + 8) = a[t];
   };
   const int first = n < 9 ? n : 9;
-  for (int i = 0; i < first; ++i) load_row(i);
+  for (int i = 0; i < first; ++i) {
+    double a[kStencil];
+    int s;
+    R.row(g, n, i, a, s);
+    store_row(i, a, s);
+  }
+  // Elimination of column k from the B rows below the pivot over the B
+  // columns to its right: every operand is read before any result is
+  // written (the rows are distinct ring slots), so the reads issue together.
+  auto eliminate = [&](auto bsz, int rk, double dinv) {
+    constexpr int B = decltype(bsz)::value;
+    double pk[B], lv[B], rw[B][B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) pk[t] = W(rk, 9 + t);
+#pragma unroll
+    for (int r = 1; r <= B; ++r) {
+      const int ri = rk + r < 9 ? rk + r : rk + r - 9;
+      lv[r - 1] = W(ri, 8 - r);
+#pragma unroll
+      for (int t = 1; t <= B; ++t) rw[r - 1][t - 1] = W(ri, 8 - r + t);
+    }
+#pragma unroll
+    for (int r = 1; r <= B; ++r) {
+      const int ri = rk + r < 9 ? rk + r : rk + r - 9;
+      const double l = lv[r - 1] * dinv;
+      W(ri, 8 - r) = l;
+#pragma unroll
+      for (int t = 1; t <= B; ++t) W(ri, 8 - r + t) = rw[r - 1][t - 1] - l * pk[t - 1];
+    }
+  };
   for (int k = 0; k < n; ++k) {
+    // the row entering the window at the end of this step: its table reads
+    // are issued first and consumed last
+    double anx[kStencil];
+    int snx = 0;
+    const bool more = k + 9 < n;
+    if (more) R.row(g, n, k + 9, anx, snx);
     const int rk = k % 9;
     const double dinv = 1.0 / W(rk, 8);
-    const int last = min(k + 8, n - 1);
-    for (int i = k + 1; i <= last; ++i) {
-      const int ri = i % 9;
-      const double l = W(ri, k - i + 8) * dinv;
-      W(ri, k - i + 8) = l;
-      if (l != 0.0)
-        for (int c = k + 1; c <= last; ++c) W(ri, c - i + 8) -= l * W(rk, c - k + 8);
-    }
+    // Rows k+5.. have no entry in column k and row k none right of k+4 when
+    // the 9-point windows of rows k-4..k+8 are all centred; near the walls
+    // the one-sided windows reach 8 rows and columns.  Columns past N-1 hold
+    // zeros in every live row; ring slots of rows past N-1 hold rows already
+    // written out, whose updates are never read.
+    if (k >= 4 && more)
+      eliminate(std::integral_constant<int, 4>{}, rk, dinv);
+    else
+      eliminate(std::integral_constant<int, 8>{}, rk, dinv);
     // row k is final
     double *v = F.vals + (size_t)k * kSlots * nops + op;
     for (int t = 1; t <= 4; ++t) {
@@ -150,7 +188,7 @@ k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_o
       for (int c = n - 9; c <= k - 5; ++c)
         if (c >= 0) F.edge[(size_t)(10 + edge_off(t) + c - (n - 9)) * nops + op] = W(rk, c - k + 8);
     }
-    if (k + 9 < n) load_row(k + 9);
+    if (more) store_row(k + 9, anx, snx);
   }
 }
 
@@ -161,13 +199,17 @@ k_factor(Dims d, Grid g, Factors F, int kind, double alpha, double beta, int q_o
 // compiler can schedule them ahead of the recurrence; only the one-sided
 // wall rows (U to column 8 in rows 0..3, L from column N-9 in rows N-4..N-1)
 // take the extra edge terms, in peeled loops.
-template <typename V, typename RHS, typename COL>
-__device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rhs, COL col) {
+template <typename V, int NR = 0, typename RHS, typename COL>
+__device__ __forceinline__ void lu_solve(const Factors &F, int op, int nrt, RHS rhs, COL col) {
+  // NR > 0: the row count is a compile-time constant and every loop unrolls
+  // fully (COL may then name registers)
+  const int n = NR > 0 ? NR : nrt;
+  constexpr int kU = NR > 0 ? NR : 4;
   const size_t nops = F.nops;
   const double *__restrict__ vals = F.vals + op;
   const double *__restrict__ edge = F.edge + op;
   V y1{}, y2{}, y3{}, y4{};
-#pragma unroll 4
+#pragma unroll kU
   for (int j = 0; j < n - 4; ++j) {
     const double *v = vals + (size_t)j * kSlots * nops;
     const double l4 = v[0], l3 = v[nops], l2 = v[2 * nops], l1 = v[3 * nops];
@@ -182,17 +224,19 @@ __device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rh
     y1 = y;
     col(j) = y;
   }
+#pragma unroll
   for (int j = n - 4; j < n; ++j) {
     const double *v = vals + (size_t)j * kSlots * nops;
     V y = rhs(j);
 #pragma unroll
     for (int t = 1; t <= 4; ++t) y = y - v[(size_t)(4 - t) * nops] * col(j - t);
     const int tt = n - 1 - j;
+#pragma unroll
     for (int c = n - 9; c <= j - 5; ++c) y = y - edge[(size_t)(10 + edge_off(tt) + c - (n - 9)) * nops] * col(c);
     col(j) = y;
   }
   V x1{}, x2{}, x3{}, x4{};
-#pragma unroll 4
+#pragma unroll kU
   for (int j = n - 1; j >= 4; --j) {
     const double *v = vals + (size_t)j * kSlots * nops;
     const double di = v[4 * nops], u1 = v[5 * nops], u2 = v[6 * nops], u3 = v[7 * nops], u4 = v[8 * nops];
@@ -208,11 +252,13 @@ __device__ __forceinline__ void lu_solve(const Factors &F, int op, int n, RHS rh
     x1 = x;
     col(j) = x;
   }
+#pragma unroll
   for (int j = 3; j >= 0; --j) {
     const double *v = vals + (size_t)j * kSlots * nops;
     V x = col(j);
 #pragma unroll
     for (int t = 1; t <= 4; ++t) x = x - v[(size_t)(4 + t) * nops] * col(j + t);
+#pragma unroll
     for (int c = j + 5; c <= 8; ++c) x = x - edge[(size_t)(edge_off(j) + c - (j + 5)) * nops] * col(c);
     col(j) = v[(size_t)4 * nops] * x;
   }
@@ -242,8 +288,78 @@ __device__ __forceinline__ Cd d1_rowc(const Grid &g, int j, const double2 *x, si
   return acc;
 }
 
-// Homogeneous responses and inverse influence matrices per (m, |k|).
-__global__ void __launch_bounds__(64) k_influence_setup(Dims d, Grid g, Factors fp, Factors fv, Influence I) {
+// Homogeneous responses and inverse influence matrices per (m, |k|), in
+// three passes: the pressure responses p_j (Neumann data e_0, e_{N-1}; do not
+// depend on the step size, computed once), then the six velocity responses
+// (X+, X-, h for each p_j) in parallel, then the 2x2 influence matrices.
+__global__ void __launch_bounds__(64) k_influence_p(Dims d, Factors fp, Influence I) {
+  const int op = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;  // 0: data at r_i, 1: at r_o
+  if (op >= I.nops) return;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = op / kp1;
+  const int ka = op - m * kp1;
+  const size_t ns = I.nops;
+  double *Pj = I.resp + (size_t)jj * n * ns + op;
+  if (m == 0 && ka == 0) {
+    for (int j = 0; j < n; ++j) Pj[(size_t)j * ns] = 0.0;
+    return;
+  }
+  const int wall = jj == 0 ? 0 : n - 1;
+  lu_solve<Rd>(fp, op, n, [&](int j) { return Rd{j == wall ? 1.0 : 0.0}; },
+               [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Pj[(size_t)j * ns]); });
+}
+
+template <bool USE_LDS>
+__global__ void __launch_bounds__(64) k_influence_x(Dims d, Grid g, Factors fv, Influence I) {
+  extern __shared__ double inf_lds[];  // USE_LDS: [2][N_r][64] pressure and solution columns
+  const int op = blockIdx.x * blockDim.x + threadIdx.x;
+  const int jj = blockIdx.y;    // which pressure response
+  const int kind = blockIdx.z;  // 0: X+, 1: X-, 2: h
+  if (op >= I.nops) return;
+  const int n = d.nr;
+  const int kp1 = d.kmax + 1;
+  const int m = op / kp1;
+  const int ka = op - m * kp1;
+  const size_t ns = I.nops;
+  double *out = I.resp + (size_t)(2 + 2 * kind + jj) * n * ns + op;
+  if (m == 0 && ka == 0) {
+    for (int j = 0; j < n; ++j) out[(size_t)j * ns] = 0.0;
+    return;
+  }
+  const double mm = (double)m;
+  const double *Pj = I.resp + (size_t)jj * n * ns + op;
+  const int q = kind == 0 ? m + 1 : (kind == 1 ? (m >= 1 ? m - 1 : 1 - m) : m);
+  // X+ = H_{m+1}^-1 (-(D1 p - m p / r)), X- = H_{|m-1|}^-1 (-(D1 p + m p / r)),
+  // h = H_m^-1 p so that X_z = -i kappa h
+  auto rhs = [&](int j, const double *p, size_t stride) {
+    if (j == 0 || j == n - 1) return Rd{0.0};
+    const double pj = p[(size_t)j * stride];
+    if (kind == 2) return Rd{pj};
+    const double dp = d1_row(g, j, p, stride);
+    const double mp = mm * g.rinv[j] * pj;
+    return Rd{kind == 0 ? -(dp - mp) : -(dp + mp)};
+  };
+  if constexpr (USE_LDS) {
+    // each lane owns one pressure column and one solution column in LDS (no
+    // sharing, so no barrier): the back substitution and the stencil reads
+    // stay on chip
+    double *pl = inf_lds + threadIdx.x;
+    double *xl = inf_lds + (size_t)n * 64 + threadIdx.x;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) pl[j * 64] = Pj[(size_t)j * ns];
+    lu_solve<Rd>(fv, q * kp1 + ka, n, [&](int j) { return rhs(j, pl, 64); },
+                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&xl[j * 64]); });
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) out[(size_t)j * ns] = xl[j * 64];
+  } else {
+    lu_solve<Rd>(fv, q * kp1 + ka, n, [&](int j) { return rhs(j, Pj, ns); },
+                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&out[(size_t)j * ns]); });
+  }
+}
+
+__global__ void __launch_bounds__(64) k_influence_a(Dims d, Grid g, Influence I) {
   const int op = blockIdx.x * blockDim.x + threadIdx.x;
   if (op >= I.nops) return;
   const int n = d.nr;
@@ -251,63 +367,16 @@ __global__ void __launch_bounds__(64) k_influence_setup(Dims d, Grid g, Factors 
   const int m = op / kp1;
   const int ka = op - m * kp1;
   const size_t ns = I.nops;
-  double *P1 = I.resp + 0 * (size_t)n * ns + op;
-  double *P2 = I.resp + 1 * (size_t)n * ns + op;
-  double *Xp1 = I.resp + 2 * (size_t)n * ns + op;
-  double *Xp2 = I.resp + 3 * (size_t)n * ns + op;
-  double *Xm1 = I.resp + 4 * (size_t)n * ns + op;
-  double *Xm2 = I.resp + 5 * (size_t)n * ns + op;
-  double *H1 = I.resp + 6 * (size_t)n * ns + op;
-  double *H2 = I.resp + 7 * (size_t)n * ns + op;
   if (m == 0 && ka == 0) {
-    for (int s = 0; s < 8; ++s)
-      for (int j = 0; j < n; ++j) I.resp[((size_t)s * n + j) * ns + op] = 0.0;
     for (int e = 0; e < 4; ++e) I.ainv[(size_t)e * ns + op] = 0.0;
     return;
   }
   const double mm = (double)m;
-  const int op_p = m * kp1 + ka;
-  const int op_plus = (m + 1) * kp1 + ka;
-  const int op_minus = (m >= 1 ? m - 1 : 1 - m) * kp1 + ka;
-  const int op_z = m * kp1 + ka;
-  // p_j: Neumann data e_0 / e_{N-1}
-  lu_solve<Rd>(fp, op_p, n, [&](int j) { return Rd{j == 0 ? 1.0 : 0.0}; },
-               [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&P1[(size_t)j * ns]); });
-  lu_solve<Rd>(fp, op_p, n, [&](int j) { return Rd{j == n - 1 ? 1.0 : 0.0}; },
-               [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&P2[(size_t)j * ns]); });
-  for (int jj = 0; jj < 2; ++jj) {
-    const double *Pj = jj == 0 ? P1 : P2;
-    double *Xp = jj == 0 ? Xp1 : Xp2;
-    double *Xm = jj == 0 ? Xm1 : Xm2;
-    double *Hh = jj == 0 ? H1 : H2;
-    // X+ = H_{m+1}^-1 (-(D1 p - m p / r)), X- = H_{|m-1|}^-1 (-(D1 p + m p / r))
-    lu_solve<Rd>(fv, op_plus, n,
-                 [&](int j) {
-                   if (j == 0 || j == n - 1) return Rd{0.0};
-                   const double dp = d1_row(g, j, Pj, ns);
-                   return Rd{-(dp - mm * g.rinv[j] * Pj[(size_t)j * ns])};
-                 },
-                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Xp[(size_t)j * ns]); });
-    lu_solve<Rd>(fv, op_minus, n,
-                 [&](int j) {
-                   if (j == 0 || j == n - 1) return Rd{0.0};
-                   const double dp = d1_row(g, j, Pj, ns);
-                   return Rd{-(dp + mm * g.rinv[j] * Pj[(size_t)j * ns])};
-                 },
-                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Xm[(size_t)j * ns]); });
-    // h = H_m^-1 p, so that X_z = -i kappa h
-    lu_solve<Rd>(fv, op_z, n,
-                 [&](int j) {
-                   if (j == 0 || j == n - 1) return Rd{0.0};
-                   return Rd{Pj[(size_t)j * ns]};
-                 },
-                 [&](int j) -> Rd & { return *reinterpret_cast<Rd *>(&Hh[(size_t)j * ns]); });
-  }
   // A[w][jj] = wall divergence of response jj (walls carry zero velocity)
   double A[2][2];
   for (int jj = 0; jj < 2; ++jj) {
-    const double *Xp = jj == 0 ? Xp1 : Xp2;
-    const double *Xm = jj == 0 ? Xm1 : Xm2;
+    const double *Xp = I.resp + (size_t)(2 + jj) * n * ns + op;
+    const double *Xm = I.resp + (size_t)(4 + jj) * n * ns + op;
     for (int w = 0; w < 2; ++w) {
       const int j = w == 0 ? 0 : n - 1;
       const double ri = g.rinv[j];
@@ -1462,13 +1531,38 @@ inline dim3 mode_grid(const nsc_ctx *c, int y, int z = 1) {
 
 hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha, double beta) {
   hipLaunchKernelGGL(k_factor, dim3((f->nops + kFacThreads - 1) / kFacThreads), dim3(kFacThreads), 0,
-                     c->stream, c->d, c->g, *f, kind, alpha, beta, 0);
+                     c->stream, c->d, c->g, *f, *f, kind, alpha, beta, beta, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor2(const nsc_ctx *c, Factors *f0, Factors *f1, int kind, double alpha,
+                          double beta0, double beta1) {
+  const int nmax = f0->nops > f1->nops ? f0->nops : f1->nops;
+  hipLaunchKernelGGL(k_factor, dim3((nmax + kFacThreads - 1) / kFacThreads, 2),
+                     dim3(kFacThreads), 0, c->stream, c->d, c->g, *f0, *f1, kind, alpha, beta0,
+                     beta1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_influence_pressure(const nsc_ctx *c) {
+  hipLaunchKernelGGL(k_influence_p, dim3((c->inf.nops + 63) / 64, 2), dim3(64), 0, c->stream, c->d,
+                     c->fp, c->inf);
   return hipGetLastError();
 }
 
 hipError_t launch_influence_setup(const nsc_ctx *c) {
-  hipLaunchKernelGGL(k_influence_setup, dim3((c->inf.nops + 63) / 64), dim3(64), 0, c->stream,
-                     c->d, c->g, c->fp, c->fv, c->inf);
+  const dim3 gx((c->inf.nops + 63) / 64, 2, 3);
+  // LDS columns only while every workgroup is resident at once: the solves
+  // are latency chains, and at larger sizes the LDS would cap the waves in
+  // flight below what the global-memory variant keeps
+  const size_t shm = (size_t)2 * c->d.nr * 64 * sizeof(double);
+  const size_t resident = shm <= (size_t)c->lds_max ? (size_t)c->cu_count * (c->lds_cu / shm) : 0;
+  if ((size_t)gx.x * gx.y * gx.z <= resident)
+    hipLaunchKernelGGL(k_influence_x<true>, gx, dim3(64), shm, c->stream, c->d, c->g, c->fv, c->inf);
+  else
+    hipLaunchKernelGGL(k_influence_x<false>, gx, dim3(64), 0, c->stream, c->d, c->g, c->fv, c->inf);
+  hipLaunchKernelGGL(k_influence_a, dim3((c->inf.nops + 63) / 64), dim3(64), 0, c->stream, c->d,
+                     c->g, c->inf);
   return hipGetLastError();
 }
 

@@ -195,8 +195,10 @@ struct StageTimer {
 int ensure_factors(nsc_ctx *c, double dt, double cc) {
   if (dt == c->fac_dt && cc == c->fac_c) return NSC_OK;
   StageTimer t(c, 10);
-  HIPCHK(launch_factor(c, &c->fv, OP_HELMHOLTZ, 1.0 / dt, cc));
-  if (c->d.heated) HIPCHK(launch_factor(c, &c->ft, OP_HELMHOLTZ, 1.0 / dt, cc / c->d.pr));
+  if (c->d.heated)
+    HIPCHK(launch_factor2(c, &c->fv, &c->ft, OP_HELMHOLTZ, 1.0 / dt, cc, cc / c->d.pr));
+  else
+    HIPCHK(launch_factor(c, &c->fv, OP_HELMHOLTZ, 1.0 / dt, cc));
   HIPCHK(launch_influence_setup(c));
   c->fac_dt = dt;
   c->fac_c = cc;
@@ -345,6 +347,14 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
             hipSuccess &&
         lds >= 32 * 1024)
       c->lds_max = lds - 1024;  // headroom for the kernels' static LDS
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        v > 0)
+      c->cu_count = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, c->device) ==
+            hipSuccess &&
+        v >= lds)
+      c->lds_cu = v;
   }
 
   // host tables
@@ -455,6 +465,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   // Delta t-independent pressure factors
   HIPCHK(launch_factor(c, &c->fp, OP_POISSON, 0.0, 0.0));
   HIPCHK(launch_factor(c, &c->fp00, OP_MEAN_PRESSURE, 0.0, 0.0));
+  HIPCHK(launch_influence_pressure(c));  // pressure responses: independent of the step size
   HIPCHK(hipStreamSynchronize(c->stream));
   return NSC_OK;
 }

@@ -79,6 +79,8 @@ struct nsc_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int lds_max = 64 * 1024;  // dynamic LDS bytes per workgroup (device limit)
+  int cu_count = 256;       // compute units
+  int lds_cu = 160 * 1024;  // LDS bytes per compute unit
   // host copies
   double *h_r = nullptr;
   // device tables
@@ -129,6 +131,11 @@ hipError_t launch_cfl_final(const nsc_ctx *c, double *out);
 
 hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha,
                          double beta);
+// two operator sets of one kind and shift alpha in one launch (betas and
+// operator counts may differ)
+hipError_t launch_factor2(const nsc_ctx *c, Factors *f0, Factors *f1, int kind, double alpha,
+                          double beta0, double beta1);
+hipError_t launch_influence_pressure(const nsc_ctx *c);
 hipError_t launch_influence_setup(const nsc_ctx *c);
 hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn,
                       const double *nq, double dt, double cc);
