@@ -69,7 +69,9 @@ def kernel_bytes(name, w, prec):
     if name == "influence":
         return 3 * 18 * nmodes * 16 + nops_m * 32 + nmodes * 32
     if name == "finalize":
-        return (F + 1) * S + nmodes * 32 + nops_m * 8 * w["N_r"] * 8 + F * S
+        # the step's variant: no pressure (read X, lambda, six response
+        # columns; write the state)
+        return F * S + nmodes * 32 + nops_m * 6 * w["N_r"] * 8 + F * S
     return 0
 
 
@@ -79,7 +81,7 @@ DEVICE_KERNEL_WORKLOAD = "tc-heated-n64"
 DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float, 192>", "theta": "nsc::k_theta<float, true, 192>",
                  "zfwd": "nsc::k_zfwd<float, 192>", "rhs": "nsc::k_rhs", "div": "nsc::k_div2",
                  "sweep_pt": "nsc::k_sweep<true, 0, 64>", "sweep_vel": "nsc::k_sweep<true, 1, 64>",
-                 "vel_rhs": "nsc::k_vel_rhs", "finalize": "nsc::k_finalize",
+                 "vel_rhs": "nsc::k_vel_rhs", "finalize": "nsc::k_finalize<false>",
                  "influence": "nsc::k_influence"}
 
 

@@ -379,14 +379,58 @@ __device__ __forceinline__ double2 spectral_terms(const Dims &d, const double2 *
   return o;
 }
 
+// Minimum of the per-line CFL bounds over the whole grid (a NaN anywhere
+// gives NaN), by one workgroup: written to the device result and, when
+// given, to a host-mapped pinned scalar, so that the host reads the bound
+// without a separate copy.
+__device__ void cfl_reduce(const double *__restrict__ part, int n, double *out, double *out_host) {
+  __shared__ double red[kFftThreads / 64];
+  auto nanmin = [](double a, double b) { return (isnan(a) || isnan(b)) ? NAN : fmin(a, b); };
+  // eight loads in flight per thread (the minimum does not depend on the order)
+  const int bd = blockDim.x;
+  double acc[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) acc[a] = DBL_MAX;
+  int i = threadIdx.x;
+  for (; i + 7 * bd < n; i += 8 * bd) {
+    double p[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) p[a] = part[i + a * bd];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) acc[a] = nanmin(acc[a], p[a]);
+  }
+  for (; i < n; i += bd) acc[0] = nanmin(acc[0], part[i]);
+  double v = acc[0];
+#pragma unroll
+  for (int a = 1; a < 8; ++a) v = nanmin(v, acc[a]);
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    v = (isnan(o) || isnan(v)) ? NAN : fmin(v, o);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)((blockDim.x + 63) >> 6); ++w)
+      r = (isnan(r) || isnan(red[w])) ? NAN : fmin(r, red[w]);
+    out[0] = r;
+    if (out_host) out_host[0] = r;
+  }
+}
+
 template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz, const C2<T> *__restrict__ W,
                        const double2 *__restrict__ u, double2 *__restrict__ nh,
                        const C2<T> *__restrict__ tw, int tm, double scale,
-                       const double *__restrict__ mean) {
+                       const double *__restrict__ mean, const double *__restrict__ cfl_part,
+                       int cfl_n, double *cfl_out, double *cfl_host) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
   C2<T> *buf = tws + d.nz;
+  // the first workgroup dispatched also reduces the CFL bounds of the theta
+  // pass (complete: that kernel ended before this one started)
+  if (cfl_out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
+    cfl_reduce(cfl_part, cfl_n, cfl_out, cfl_host);
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
@@ -423,26 +467,6 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
   }
 }
 
-__global__ void k_cfl_final(const double *__restrict__ part, int n, double *out) {
-  __shared__ double red[16];
-  double v = DBL_MAX;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double p = part[i];
-    v = (isnan(v) || isnan(p)) ? NAN : fmin(v, p);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    double o = __shfl_down(v, off, 64);
-    v = (isnan(o) || isnan(v)) ? NAN : fmin(v, o);
-  }
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-      r = (isnan(r) || isnan(red[w])) ? NAN : fmin(r, red[w]);
-    out[0] = r;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Vector--Jacobian product of the nonlinear term.  With the inverse transform
@@ -779,7 +803,8 @@ hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
 }
 
 template <typename T>
-hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw) {
+hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw, double *cfl_out,
+                     double *cfl_host) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
   const int threads = z_threads(c->plan_z, tm);
@@ -789,7 +814,8 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw)
     hipLaunchKernelGGL((k_zfwd<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
                        c->d, c->g, c->plan_z, reinterpret_cast<const C2<T> *>(c->wbuf),
                        reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
-                       reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean);
+                       reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean, c->cfl_part,
+                       c->cfl_nblk, cfl_out, cfl_host);
     return hipGetLastError();
   });
 }
@@ -856,15 +882,10 @@ hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl) {
   return theta_impl<double>(c, c->tw64_t, want_cfl);
 }
 
-hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat) {
-  if (prec == NSC_MIXED) return zfwd_impl<float>(c, u, n_hat, c->tw32_z);
-  return zfwd_impl<double>(c, u, n_hat, c->tw64_z);
-}
-
-hipError_t launch_cfl_final(const nsc_ctx *c, double *out) {
-  hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, c->stream, c->cfl_part,
-                     c->cfl_nblk, out);
-  return hipGetLastError();
+hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat, double *cfl_out,
+                       double *cfl_host) {
+  if (prec == NSC_MIXED) return zfwd_impl<float>(c, u, n_hat, c->tw32_z, cfl_out, cfl_host);
+  return zfwd_impl<double>(c, u, n_hat, c->tw64_z, cfl_out, cfl_host);
 }
 
 hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, const double *nbar,

@@ -775,6 +775,8 @@ struct Vals {
   Cd ur, ut, uz, T, p;
 };
 
+// WITH_P: also the pressure (the step itself does not need it)
+template <bool WITH_P = true>
 __device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
                                             const double2 *__restrict__ sx,
                                             const double2 *__restrict__ sp,
@@ -788,7 +790,7 @@ __device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
   Cd xp = ld(sx + (size_t)j * P + md);
   Cd xm = ld(sx + ((size_t)n + j) * P + md);
   Cd xz = ld(sx + ((size_t)2 * n + j) * P + md);
-  Cd p = ld(sp + (size_t)j * P + md);
+  Cd p = WITH_P ? ld(sp + (size_t)j * P + md) : Cd{0.0, 0.0};
   Vals v;
   if (!(m == 0 && ka == 0)) {
     const double kap = (double)(kk - d.kmax) * d.kz;
@@ -796,7 +798,7 @@ __device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
     const size_t ns = I.nops;
     const int op = m * kp1 + ka;
     auto Rv = [&](int s) { return I.resp[((size_t)s * n + j) * ns + op]; };
-    p = p + Rv(0) * l1 + Rv(1) * l2;
+    if (WITH_P) p = p + Rv(0) * l1 + Rv(1) * l2;
     xp = xp + Rv(2) * l1 + Rv(3) * l2;
     xm = xm + Rv(4) * l1 + Rv(5) * l2;
     // X_z,j = -i kappa h_j
@@ -812,6 +814,7 @@ __device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
   return v;
 }
 
+template <bool WITH_P>
 __global__ void k_finalize(Dims d, Influence I, const double2 *__restrict__ sx,
                            const double2 *__restrict__ sp, const double2 *__restrict__ lam,
                            double2 *__restrict__ out, double2 *__restrict__ pout) {
@@ -820,9 +823,9 @@ __global__ void k_finalize(Dims d, Influence I, const double2 *__restrict__ sx,
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
-  Vals v = final_value(d, I, sx, sp, lam, j, md);
+  Vals v = final_value<WITH_P>(d, I, sx, sp, lam, j, md);
   if (md < d.mz) {  // m = 0: Hermitian projection
-    Vals w = final_value(d, I, sx, sp, lam, j, d.mz - 1 - md);
+    Vals w = final_value<WITH_P>(d, I, sx, sp, lam, j, d.mz - 1 - md);
     auto h = [](Cd a, Cd b) { return Cd{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)}; };
     v.ur = h(v.ur, w.ur);
     v.ut = h(v.ut, w.ut);
@@ -834,7 +837,7 @@ __global__ void k_finalize(Dims d, Influence I, const double2 *__restrict__ sx,
   st(out + ((size_t)1 * n + j) * P + md, v.ut);
   st(out + ((size_t)2 * n + j) * P + md, v.uz);
   if (d.heated) st(out + ((size_t)3 * n + j) * P + md, v.T);
-  if (pout) st(pout + (size_t)j * P + md, v.p);
+  if (WITH_P) st(pout + (size_t)j * P + md, v.p);
 }
 
 // Perturbation energy partial sums: w_j r_j c_m |u - U_b|^2 per block.
@@ -1583,7 +1586,8 @@ hipError_t launch_influence(const nsc_ctx *c) {
 }
 
 hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out) {
-  hipLaunchKernelGGL(k_finalize, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->inf,
+  auto fin = p_out ? k_finalize<true> : k_finalize<false>;
+  hipLaunchKernelGGL(fin, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->inf,
                      reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<const double2 *>(c->s_p),
                      reinterpret_cast<const double2 *>(c->s_lam), reinterpret_cast<double2 *>(out),
                      reinterpret_cast<double2 *>(p_out));

@@ -205,7 +205,8 @@ int ensure_factors(nsc_ctx *c, double dt, double cc) {
   return NSC_OK;
 }
 
-int nonlinear_impl(nsc_ctx *c, const double *u, double *nh, double *cfl_out) {
+int nonlinear_impl(nsc_ctx *c, const double *u, double *nh, double *cfl_out,
+                   double *cfl_host = nullptr) {
   {
     StageTimer t(c, 0);
     HIPCHK(launch_zinv(c, c->precision, u));
@@ -216,11 +217,7 @@ int nonlinear_impl(nsc_ctx *c, const double *u, double *nh, double *cfl_out) {
   }
   {
     StageTimer t(c, 2);
-    HIPCHK(launch_zfwd(c, c->precision, u, nh));
-  }
-  if (cfl_out) {
-    StageTimer t(c, 3);
-    HIPCHK(launch_cfl_final(c, cfl_out));
+    HIPCHK(launch_zfwd(c, c->precision, u, nh, cfl_out, cfl_out ? cfl_host : nullptr));
   }
   return NSC_OK;
 }
@@ -445,6 +442,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   TRY(dmalloc((void **)&c->s_adj, field * c->n_in));
   TRY(dmalloc((void **)&c->s_mean, (size_t)8 * n * sizeof(double)));
   HIPCHK(hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault));
+  HIPCHK(hipHostGetDevicePointer((void **)&c->h_pinned_dev, c->h_pinned, 0));
   HIPCHK(hipEventCreateWithFlags(&c->ev_cfl, hipEventDisableTiming));
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
@@ -533,11 +531,9 @@ int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
   const double dt = *dt_inout;
   if (!(dt > 0.0 && std::isfinite(dt))) return NSC_ERR_ARG;
   const bool dyn = c->dynamic != 0;
-  TRY(nonlinear_impl(c, u, c->s_nn, dyn ? c->cfl_val : nullptr));
-  if (dyn) {
-    HIPCHK(hipMemcpyAsync(c->h_pinned, c->cfl_val, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
-  }
+  // the bound lands in the host-mapped pinned scalar; the event marks it
+  TRY(nonlinear_impl(c, u, c->s_nn, dyn ? c->cfl_val : nullptr, c->h_pinned_dev));
+  if (dyn) HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
   // predictor, then correctors; the last stage writes u in place (the
   // finalising kernel reads only library scratch, never u^n)
   TRY(solve_impl(c, u, c->s_nn, c->s_nn, c->n_corr == 0 ? u : c->s_u1, nullptr, dt, c->c, 1));

@@ -113,6 +113,7 @@ struct nsc_ctx {
   double *s_adj = nullptr;  // [n_in][N_r][modes] complex adjoint of the derived fields
   double *s_mean = nullptr;  // [8][N_r] mean-flow profiles of the current nonlinear call
   double *h_pinned = nullptr;  // pinned host scalar(s)
+  double *h_pinned_dev = nullptr;  // its device-side address (kernels write the CFL bound)
   hipEvent_t ev_cfl = nullptr;
   // profiling
   int profiling = 0;
@@ -126,8 +127,11 @@ namespace nsc {
 // ---- launchers (kernels in *.hip) -----------------------------------------
 hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u);
 hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl);
-hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat);
-hipError_t launch_cfl_final(const nsc_ctx *c, double *out);
+// cfl_out (device, or null): the minimum CFL bound of the preceding theta
+// pass, reduced by the z-forward kernel; cfl_host: null or a host-mapped
+// pinned scalar receiving the same value
+hipError_t launch_zfwd(const nsc_ctx *c, int prec, const double *u, double *n_hat, double *cfl_out,
+                       double *cfl_host);
 
 hipError_t launch_factor(const nsc_ctx *c, Factors *f, int kind, double alpha,
                          double beta);
