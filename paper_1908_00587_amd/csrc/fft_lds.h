@@ -153,16 +153,6 @@ __device__ __forceinline__ int PD(int i) { return i + (i >> pad_shift<T>()); }
 template <typename T>
 __host__ __device__ constexpr int lds_line(int n) { return n + (n >> pad_shift<T>()) + 1; }
 
-// XCD-aware workgroup order: the dispatcher hands consecutive workgroups to
-// the 8 XCDs in turn, each with its own L2.  Remapping the linear workgroup
-// id gives every XCD a contiguous range of logical tiles, so neighbouring
-// tiles (which share cache lines of the transposed intermediates) meet in
-// the same L2.
-__device__ __forceinline__ int xcd_remap(int w, int G) {
-  const int q = G / 8, r = G % 8;
-  const int x = w % 8, l = w / 8;
-  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
 
 // Logical (x, y, z) block coordinates after the XCD remap.
 __device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz) {

@@ -482,9 +482,16 @@ k_sweep(Dims d, SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cd *col = reinterpret_cast<Cd *>(smem);
   const int lane = threadIdx.x;
-  const int md = blockIdx.x * kSweepLanes + lane;
+  // logical (mode tile, system) after the XCD remap, system fastest: the
+  // two halves of a tile row (m, +-k) use the same operators, and the
+  // systems of neighbouring rows share them (q = m - 1, m, m + 1), so these
+  // workgroups run next to each other on one XCD and read the factors from
+  // its L2 instead of HBM
+  const int L = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int sys = L % gridDim.y;
+  const int md = (L / gridDim.y) * kSweepLanes + lane;
   if (md >= d.nmodes) return;
-  const SweepSys &S = a.s[blockIdx.y];
+  const SweepSys &S = a.s[sys];
   const size_t P = d.nmodes;
   const int n = NR > 0 ? NR : d.nr;
   constexpr int kUnrollCol = NR > 0 ? NR : 8;   // column copies
@@ -736,8 +743,12 @@ __global__ void k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__rest
 }
 
 // lambda = -A^-1 beta(X0), beta = divergence at the two walls.
-__global__ void k_influence(Dims d, Grid g, Influence I, const double2 *__restrict__ sx,
-                            double2 *__restrict__ lam) {
+// One lane per mode, 64-lane workgroups (more of the chip for a small
+// grid); the wall windows start at 0 and N-9, so all 38 loads of a lane are
+// independent and issue together.
+__global__ void __launch_bounds__(64) k_influence(Dims d, Grid g, Influence I,
+                                                  const double2 *__restrict__ sx,
+                                                  double2 *__restrict__ lam) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
@@ -755,11 +766,20 @@ __global__ void k_influence(Dims d, Grid g, Influence I, const double2 *__restri
   const double mm = (double)m;
   const double2 *xp = sx + md, *xm = sx + (size_t)n * P + md, *xz = sx + (size_t)2 * n * P + md;
   Cd beta[2];
+#pragma unroll
   for (int w = 0; w < 2; ++w) {
     const int j = w == 0 ? 0 : n - 1;
+    const int s0 = w == 0 ? 0 : n - kStencil;  // one-sided wall window
+    const double *wd = g.d1 + j * kStencil;
     const double ri = g.rinv[j];
-    beta[w] = 0.5 * ((d1_rowc(g, j, xp, P) + ((1.0 + mm) * ri) * ld(xp + (size_t)j * P)) +
-                     (d1_rowc(g, j, xm, P) + ((1.0 - mm) * ri) * ld(xm + (size_t)j * P))) +
+    Cd dp = {0.0, 0.0}, dm = {0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < kStencil; ++t) {
+      dp = fmac(wd[t], ld(xp + (size_t)(s0 + t) * P), dp);
+      dm = fmac(wd[t], ld(xm + (size_t)(s0 + t) * P), dm);
+    }
+    beta[w] = 0.5 * ((dp + ((1.0 + mm) * ri) * ld(xp + (size_t)j * P)) +
+                     (dm + ((1.0 - mm) * ri) * ld(xm + (size_t)j * P))) +
               kap * ci(ld(xz + (size_t)j * P));
   }
   const int op = m * kp1 + ka;
@@ -1580,7 +1600,7 @@ hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const
 }
 
 hipError_t launch_influence(const nsc_ctx *c) {
-  hipLaunchKernelGGL(k_influence, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->g, c->inf,
+  hipLaunchKernelGGL(k_influence, dim3((c->d.nmodes + 63) / 64), dim3(64), 0, c->stream, c->d, c->g, c->inf,
                      reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<double2 *>(c->s_lam));
   return hipGetLastError();
 }

@@ -161,4 +161,15 @@ hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, con
 // operator kinds for launch_factor
 enum { OP_HELMHOLTZ = 0, OP_POISSON = 1, OP_MEAN_PRESSURE = 2 };
 
+// XCD-aware workgroup order: the dispatcher hands consecutive workgroups to
+// the 8 XCDs in turn, each with its own L2.  Remapping the linear workgroup
+// id gives every XCD a contiguous range of logical tiles, so neighbouring
+// tiles (which share cache lines: transposed intermediates, stencil rows,
+// operator factors) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int w, int G) {
+  const int q = G / 8, r = G % 8;
+  const int x = w % 8, l = w / 8;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 }  // namespace nsc
