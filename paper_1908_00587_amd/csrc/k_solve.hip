@@ -110,13 +110,9 @@ k_factor(Dims d, Grid g, Factors F0, Factors F1, int kind, double alpha, double 
   const double kap = (double)ka * d.kz;
   OpRow R{kind, alpha, beta, (double)q * (double)q, kap * kap};
   const size_t nops = F.nops;
-  // singular pure-Neumann operator (q = 0, kappa = 0): not used
-  if (kind == OP_POISSON && q == 0 && ka == 0) {
-    for (int j = 0; j < n; ++j)
-      for (int sl = 0; sl < kSlots; ++sl) F.vals[((size_t)j * kSlots + sl) * nops + op] = 0.0;
-    for (int e = 0; e < kEdge; ++e) F.edge[(size_t)e * nops + op] = 0.0;
-    return;
-  }
+  // the pure-Neumann Poisson operator of (q = 0, kappa = 0) is singular and
+  // never used; its slot holds the mean pressure-head operator instead
+  if (kind == OP_POISSON && q == 0 && ka == 0) R.kind = OP_MEAN_PRESSURE;
   auto store_row = [&](int i, const double *a, int s) {
     const int ring = i % 9;
     for (int bi = 0; bi < kBW; ++bi) W(ring, bi) = 0.0;
@@ -454,10 +450,15 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
 // loads of later rows can be scheduled ahead; the solution is copied out at
 // the end.  Columns longer than the LDS budget keep y in the output array.
 // ---------------------------------------------------------------------------
+// Fourth word of a raw buffer resource on CDNA (gfx9 family): 32-bit data
+// format, no swizzle; with stride 0 the record count is a byte count and
+// loads past it return zero.
+constexpr int kBufferWord3 = 0x00020000;
+
 struct SweepSys {
-  Factors F, F00;
+  Factors F;
   int qmode;   // 0: q = m, 1: q = m + 1, 2: q = |m - 1|
-  int mode00;  // 0: regular operator, 1: use F00 (single op), 2: write zeros
+  int zero00;  // 1: mode (0,0) writes zeros (else its operator slot is used)
   const double2 *in;  // right side column base, rows strided by the mode count
   double2 *out;       // solution column base
 };
@@ -466,9 +467,14 @@ struct SweepArgs {
 };
 constexpr int kSweepLanes = 64;
 
-constexpr int kPf = 16;  // factor rows in flight per sweep
-constexpr int kPc = 4;   // column entries read ahead per sweep (divides kPf)
-static_assert(kPf % kPc == 0, "the column ring follows the factor ring");
+// factor rows in flight per sweep: fully unrolled 64-row sweeps (issued in
+// that order by scheduling barriers; 8 to 16 rows measure the same), and
+// runtime row counts
+constexpr int kPfUnrolled = 12;
+constexpr int kPfRuntime = 16;
+constexpr int kPc = 4;  // column entries read ahead per sweep (divides the ring depths)
+static_assert(kPfUnrolled % kPc == 0 && kPfRuntime % kPc == 0,
+              "the column ring follows the factor ring");
 
 // FAMILY only names the launch (0: pressure/temperature, 1: velocity), so
 // that profiles tell the two apart; the code is the same.
@@ -496,24 +502,22 @@ k_sweep(Dims d, SweepArgs a) {
   const int n = NR > 0 ? NR : d.nr;
   constexpr int kUnrollCol = NR > 0 ? NR : 8;   // column copies
   constexpr int kUnrollRows = NR > 0 ? NR : 1;  // row groups of the sweeps
+  constexpr int kPf = NR > 0 ? kPfUnrolled : kPfRuntime;
   const int kp1 = d.kmax + 1;
   const int m = md / d.mz;
   const int kk = md - m * d.mz;
   const int ka = kk >= d.kmax ? kk - d.kmax : d.kmax - kk;
   const double2 *__restrict__ b = S.in + md;
   double2 *__restrict__ x = S.out + md;
-  Factors F = S.F;
+  // one factor set for the whole workgroup (its base stays in scalar
+  // registers); mode (0,0) of the pressure uses slot 0 of the same set,
+  // which holds the mean pressure-head operator
+  const Factors F = S.F;
   const int q = S.qmode == 0 ? m : (S.qmode == 1 ? m + 1 : (m >= 1 ? m - 1 : 1 - m));
-  int op = q * kp1 + ka;
-  if (m == 0 && ka == 0) {
-    if (S.mode00 == 2) {
-      for (int j = 0; j < n; ++j) x[(size_t)j * P] = make_double2(0.0, 0.0);
-      return;
-    }
-    if (S.mode00 == 1) {
-      F = S.F00;
-      op = 0;
-    }
+  const int op = q * kp1 + ka;
+  if (m == 0 && ka == 0 && S.zero00) {
+    for (int j = 0; j < n; ++j) x[(size_t)j * P] = make_double2(0.0, 0.0);
+    return;
   }
   if (!USE_LDS) {
     lu_solve<Cd>(F, op, n, [&](int j) { return ld(b + (size_t)j * P); },
@@ -533,22 +537,47 @@ k_sweep(Dims d, SweepArgs a) {
   // workgroup: registers are plentiful, and the distance of these requests
   // is what hides the memory latency of the recurrences.
   const int nm = n - 4;
-  auto row = [&](int j, int sl) { return vals[((size_t)j * kSlots + sl) * nops]; };
+  // Fully unrolled sweeps read the factor rows as raw buffer loads: the
+  // lane's operator offset in one 32-bit register, the row and slot offset
+  // in a scalar register, so no 64-bit address is formed per load and the
+  // registers go to rows in flight (the host picks this variant only while
+  // the factor array spans less than 2^31 bytes).
+  const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double *>(F.vals), 0, (int)((size_t)n * kSlots * nops * sizeof(double)),
+      kBufferWord3);
+  const int voff = op * (int)sizeof(double);
+  auto row = [&](int j, int sl) -> double {
+    if constexpr (NR > 0)
+      return __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(
+                      frs, voff, (int)(((size_t)j * kSlots + sl) * nops * sizeof(double)), 0));
+    else
+      return vals[((size_t)j * kSlots + sl) * nops];
+  };
   // last four rows (forward) and first four rows (backward): band entries
-  // and the extra envelope entries
+  // and the extra envelope entries, requested kPf rows before their use so
+  // that they do not hold registers through the bulk of the sweeps
   double lt[4][4], le[10], ut[4][5], ue[10];
+  auto load_tail = [&] {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) lt[r][t] = row(nm + r, t);
+      for (int t = 0; t < 4; ++t) lt[r][t] = row(nm + r, t);
 #pragma unroll
-    for (int t = 0; t < 5; ++t) ut[r][t] = row(r, 4 + t);
-  }
+    for (int e = 0; e < 10; ++e) le[e] = edge[(size_t)(10 + e) * nops];
+  };
+  auto load_head = [&] {
 #pragma unroll
-  for (int e = 0; e < 10; ++e) {
-    le[e] = edge[(size_t)(10 + e) * nops];
-    ue[e] = edge[(size_t)e * nops];
-  }
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int t = 0; t < 5; ++t) ut[r][t] = row(r, 4 + t);
+#pragma unroll
+    for (int e = 0; e < 10; ++e) ue[e] = edge[(size_t)e * nops];
+  };
+  // (runtime row counts: at the start of each sweep)
+  const int tail_at = NR > 0 && nm - kPf > 0 ? nm - kPf : 0;          // forward row
+  const int head_at = NR > 0 && 4 + kPf < n - 1 ? 4 + kPf : n - 1;    // backward row
+  if (tail_at == 0) load_tail();
   double fa[kPf][4];
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
@@ -565,6 +594,7 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
     for (int r = 0; r < kPf; ++r) {
       const int j = j0 + r;
+      if (j == tail_at && j > 0) load_tail();
       if (j < nm) {
         // oldest terms first: the newest value y1 enters last, so the
         // row-to-row dependency is a single fused multiply-add
@@ -585,6 +615,9 @@ k_sweep(Dims d, SweepArgs a) {
       const int jn = j + kPf < nm ? j + kPf : nm - 1;
 #pragma unroll
       for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
+      // keep the source order: the loads of row jn go out now, not next to
+      // their use kPf rows later
+      if constexpr (NR > 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
@@ -600,6 +633,7 @@ k_sweep(Dims d, SweepArgs a) {
     C(j) = y;
   }
   // back substitution over rows N-1..4
+  if (head_at == n - 1) load_head();
   double u[kPf][5];
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
@@ -615,6 +649,7 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
     for (int r = 0; r < kPf; ++r) {
       const int j = j0 - r;
+      if (j == head_at && j < n - 1) load_head();
       if (j >= 4) {
         const int i = r % kPc;  // = (n - 1 - j) mod kPc
         Cd xv = cb[i];
@@ -635,6 +670,9 @@ k_sweep(Dims d, SweepArgs a) {
       const int jn = j - kPf >= 4 ? j - kPf : 4;
 #pragma unroll
       for (int t = 0; t < 5; ++t) u[r][t] = row(jn, 4 + t);
+      // keep the source order: the loads of row jn go out now, not next to
+      // their use kPf rows later
+      if constexpr (NR > 0) __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
@@ -1721,7 +1759,11 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   auto launch = [&](const SweepArgs &a, int nsys, auto family) {
     constexpr int FAM = decltype(family)::value;
     dim3 gr((d.nmodes + kSweepLanes - 1) / kSweepLanes, nsys);
-    if (lds && d.nr == 64)
+    // the unrolled variant addresses its factors with 32-bit buffer offsets
+    const bool fits = (size_t)d.nr * kSlots * sizeof(double) *
+                          (size_t)(c->fv.nops > c->fp.nops ? c->fv.nops : c->fp.nops) <
+                      ((size_t)1 << 31);
+    if (lds && d.nr == 64 && fits)
       hipLaunchKernelGGL((k_sweep<true, FAM, 64>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
     else if (lds)
       hipLaunchKernelGGL((k_sweep<true, FAM, 0>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
@@ -1736,16 +1778,16 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   } else if (stage == 1) {
     // pressure (s_g -> s_p) and temperature (s_f[3] -> s_x[3]) in one launch
     SweepArgs a{};
-    a.s[0] = SweepSys{c->fp, c->fp00, 0, wp ? 1 : 2, sg, sp};
-    if (d.heated) a.s[1] = SweepSys{c->ft, c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
+    a.s[0] = SweepSys{c->fp, 0, wp ? 0 : 1, sg, sp};
+    if (d.heated) a.s[1] = SweepSys{c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
     launch(a, d.heated ? 2 : 1, std::integral_constant<int, 0>{});
   } else if (stage == 2) {
     hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls);
   } else {
     SweepArgs av{};
-    av.s[0] = SweepSys{c->fv, c->fv, 1, 0, sf, sx};
-    av.s[1] = SweepSys{c->fv, c->fv, 2, 0, sf + fld, sx + fld};
-    av.s[2] = SweepSys{c->fv, c->fv, 0, 0, sf + 2 * fld, sx + 2 * fld};
+    av.s[0] = SweepSys{c->fv, 1, 0, sf, sx};
+    av.s[1] = SweepSys{c->fv, 2, 0, sf + fld, sx + fld};
+    av.s[2] = SweepSys{c->fv, 0, 0, sf + 2 * fld, sx + 2 * fld};
     launch(av, 3, std::integral_constant<int, 1>{});
   }
   return hipGetLastError();

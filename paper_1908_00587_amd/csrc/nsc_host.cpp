@@ -287,7 +287,6 @@ int nsc_destroy(nsc_ctx *c) {
   free_factors(&c->fv);
   free_factors(&c->ft);
   free_factors(&c->fp);
-  free_factors(&c->fp00);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->ev_cfl) (void)hipEventDestroy(c->ev_cfl);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -452,17 +451,12 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   TRY(alloc_factors(&c->fv, d.mt + 1, kp1, n));
   TRY(alloc_factors(&c->fp, d.mt, kp1, n));
   if (d.heated) TRY(alloc_factors(&c->ft, d.mt, kp1, n));
-  c->fp00.nq = 1;
-  c->fp00.nops = 1;
-  TRY(dmalloc((void **)&c->fp00.vals, (size_t)n * kSlots * sizeof(double)));
-  TRY(dmalloc((void **)&c->fp00.edge, (size_t)kEdge * sizeof(double)));
   c->inf.nops = d.mt * kp1;
   TRY(dmalloc((void **)&c->inf.resp, (size_t)8 * n * c->inf.nops * sizeof(double)));
   TRY(dmalloc((void **)&c->inf.ainv, (size_t)4 * c->inf.nops * sizeof(double)));
 
-  // Delta t-independent pressure factors
+  // Delta t-independent pressure factors (slot (0,0): the mean pressure head)
   HIPCHK(launch_factor(c, &c->fp, OP_POISSON, 0.0, 0.0));
-  HIPCHK(launch_factor(c, &c->fp00, OP_MEAN_PRESSURE, 0.0, 0.0));
   HIPCHK(launch_influence_pressure(c));  // pressure responses: independent of the step size
   HIPCHK(hipStreamSynchronize(c->stream));
   return NSC_OK;

@@ -90,7 +90,7 @@ struct nsc_ctx {
   float *tw32_t = nullptr, *tw32_z = nullptr;
   nsc::FftPlan plan_t{}, plan_z{};
   // factors
-  nsc::Factors fv{}, ft{}, fp{}, fp00{};
+  nsc::Factors fv{}, ft{}, fp{};
   nsc::Influence inf{};
   // workspaces
   void *zbuf = nullptr;    // [n_in][N_r][N_z][M_theta] complex (FP64 size)
