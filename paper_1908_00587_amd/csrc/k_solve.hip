@@ -1232,11 +1232,12 @@ k_adj_vel(Dims d, Grid g, Factors fv, Factors ft, const double2 *__restrict__ sx
 constexpr int kPfT = 8;
 
 template <int NR, class COL>
-__device__ __forceinline__ void sweep_t_lds(const double *__restrict__ vals,
-                                            const double *__restrict__ edge, size_t nops, int nrt,
-                                            COL C) {
+__device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, COL C) {
   const int n = NR > 0 ? NR : nrt;
   constexpr int kUnrollRows = NR > 0 ? NR : 1;
+  const size_t nops = F.nops;
+  const double *__restrict__ vals = F.vals + op;
+  const double *__restrict__ edge = F.edge + op;
   auto V = [&](int row, int slot) { return vals[((size_t)row * kSlots + slot) * nops]; };
   // U^T y = b: rows 0..8 with the top envelope entries
   {
@@ -1423,7 +1424,7 @@ k_adj_sweep(Dims d, Grid g, Factors fv, Factors ft, Factors fp, int kind,
       C(j) = v;
     }
   }
-  sweep_t_lds<NR>(F.vals + op, F.edge + op, F.nops, n, C);
+  sweep_t_lds<NR>(F, op, n, C);
   C(0) = Cd{0, 0};
   C(n - 1) = Cd{0, 0};
   if (kind == 0 && zero && comp == 0) {  // fbar+ = (i/2) rbar_theta, fbar- = -(i/2) rbar_theta
@@ -1689,7 +1690,8 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
   const bool lds = col_bytes <= 64 * 1024;
   const dim3 lg((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, c->d.heated ? 4 : 3);
   const dim3 lg1((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, 1);
-  if (lds && c->d.nr == 64)
+  const bool unrolled = lds && c->d.nr == 64;
+  if (unrolled)
     hipLaunchKernelGGL(k_adj_sweep<64>, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
                        c->fv, c->ft, c->fp, 0, sx, lam, sf);
   else if (lds)
@@ -1699,7 +1701,7 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
     hipLaunchKernelGGL(k_adj_vel, mode_grid(c, c->d.heated ? 4 : 3), dim3(256), 0, c->stream, c->d,
                        c->g, c->fv, c->ft, sx, lam, sf);
   hipLaunchKernelGGL(k_adj_pbar, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sp);
-  if (lds && c->d.nr == 64)
+  if (unrolled)
     hipLaunchKernelGGL(k_adj_sweep<64>, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
                        c->fv, c->ft, c->fp, 1, sp, lam, sg);
   else if (lds)
