@@ -165,9 +165,11 @@ __device__ __forceinline__ void xcd_block(int &bx, int &by, int &bz) {
   bz = L / (gx * gy);
 }
 
-// As xcd_block, with z varying fastest in the logical order: the workgroups
-// of all fields of one (x, y) tile run next to each other on one XCD, so the
-// spectral rows they share are read from HBM once and then from its L2.
+// As xcd_block, with z varying fastest in the logical order, then y: the
+// workgroups of all fields of one (x, y) tile run next to each other on one
+// XCD, and consecutive tiles step along y (the radial row) for a fixed x, so
+// the 9-row stencil window a tile reads stays small enough for that XCD's
+// L2 and most rows come from it instead of HBM.
 __device__ __forceinline__ void xcd_block_zfirst(int &bx, int &by, int &bz) {
   const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
   const int G = gx * gy * gz;
@@ -175,8 +177,8 @@ __device__ __forceinline__ void xcd_block_zfirst(int &bx, int &by, int &bz) {
   const int L = xcd_remap(w, G);
   bz = L % gz;
   const int rest = L / gz;
-  bx = rest % gx;
-  by = rest / gx;
+  by = rest % gy;
+  bx = rest / gy;
 }
 
 // Copy the n twiddles of a plan into LDS (caller synchronises).
