@@ -57,7 +57,12 @@ enum {
   NSC_ERR_OOM = -3,       /* device allocation failed or size overflow       */
   NSC_ERR_NONFINITE = -4, /* NaN/Inf detected in a reduction                 */
   NSC_ERR_DT = -5,        /* time step collapsed below 1e-12                 */
-  NSC_ERR_STATE = -6      /* call not valid in the context's current state   */
+  NSC_ERR_STATE = -6      /* call not valid in the context's current state:
+                           * also the nonlinear term (and its VJP) at a
+                           * precision whose theta line set (all fields of
+                           * one (r, z) line, padded, with the twiddles) does
+                           * not fit one workgroup's LDS -- FP64 with
+                           * N_theta = 1536; the mixed precision fits */
 };
 
 enum { NSC_FP64 = 0, NSC_MIXED = 1 };

@@ -877,6 +877,12 @@ hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u) {
   return zinv_impl<double>(c, u, c->tw64_z);
 }
 
+bool theta_fits(const nsc_ctx *c, int prec, int adjoint) {
+  const int npi = (c->n_in + 1) / 2;
+  const size_t esize = prec == NSC_MIXED ? sizeof(C2<float>) : sizeof(C2<double>);
+  return theta_launch(c, adjoint ? npi + 2 : npi, esize).shm <= (size_t)c->lds_max;
+}
+
 hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl) {
   if (prec == NSC_MIXED) return theta_impl<float>(c, c->tw32_t, want_cfl);
   return theta_impl<double>(c, c->tw64_t, want_cfl);

@@ -207,6 +207,7 @@ int ensure_factors(nsc_ctx *c, double dt, double cc) {
 
 int nonlinear_impl(nsc_ctx *c, const double *u, double *nh, double *cfl_out,
                    double *cfl_host = nullptr) {
+  if (!theta_fits(c, c->precision, 0)) return NSC_ERR_STATE;
   {
     StageTimer t(c, 0);
     HIPCHK(launch_zinv(c, c->precision, u));
@@ -569,6 +570,7 @@ int nsc_nonlinear_vjp(nsc_ctx *c, const double *u, const double *nbar, double *u
   if (!c || !u || !nbar || !ubar) return NSC_ERR_ARG;
   if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)nbar)
     return NSC_ERR_ARG;
+  if (!theta_fits(c, c->precision, 1)) return NSC_ERR_STATE;
   HIPCHK(launch_nonlinear_vjp(c, c->precision, u, nbar, ubar));
   return NSC_OK;
 }
@@ -612,6 +614,7 @@ int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double
   const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
   const int nc = c->n_corr;
   if (ubar < stages + (size_t)nc * fld && stages < ubar + fld) return NSC_ERR_ARG;
+  if (!theta_fits(c, c->precision, 1)) return NSC_ERR_STATE;
   if (!c->s_vjp) TRY(dmalloc((void **)&c->s_vjp, 4 * fld * sizeof(double)));
   double *abar = c->s_vjp, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
   TRY(ensure_factors(c, c->dt, c->c));

@@ -127,6 +127,9 @@ namespace nsc {
 // ---- launchers (kernels in *.hip) -----------------------------------------
 hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u);
 hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl);
+// whether one theta workgroup's line set (all fields of an (r, z) line, with
+// the twiddles) fits the LDS at this precision; adjoint: the transposed pass
+bool theta_fits(const nsc_ctx *c, int prec, int adjoint);
 // cfl_out (device, or null): the minimum CFL bound of the preceding theta
 // pass, reduced by the z-forward kernel; cfl_host: null or a host-mapped
 // pinned scalar receiving the same value

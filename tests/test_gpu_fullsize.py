@@ -114,3 +114,60 @@ def test_step_full_size_heated(prec, tol):
     torch.cuda.synchronize()
     for f in range(p.F):
         assert rel(u[f], ref[f]) < tol, f
+
+
+CONV = "tc-conv-n256"
+CONV_ROWS = [0, 131, 255]
+CONV_MODES = [(0, 511), (0, 10), (0, 1000), (1, 511), (100, 300), (511, 0), (511, 1022)]
+
+
+def test_conv_full_size_sampled():
+    """The largest workload on one GPU (N_r = 256, 512 x 1023 modes, padded
+    1536 x 1536 planes; about 130 GiB of library buffers): sampled radial
+    rows of the mixed-precision nonlinear term and sampled modes of the FP64
+    implicit stage against the oracle.  The FP64 nonlinear term, whose theta
+    line set does not fit one workgroup's LDS at this size, is refused."""
+    import paper_1908_00587_amd as nsc
+    _say("conv full size: inputs")
+    p = O.Params(*params(CONV))
+    u = O.base_state(p)
+    u += 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 91)
+    ctx = _ctx(CONV, "mixed")
+    ug = u.cuda()
+    _say("conv full size: mixed nonlinear")
+    out, c = ctx.nonlinear(ug, cfl=True)
+    torch.cuda.synchronize()
+    got = out[:, CONV_ROWS].cpu()
+    c = float(c.cpu()[0])
+    del out
+    _say("conv full size: oracle rows")
+    ref, dt_rows = O.nonlinear_planes(p, u, torch.tensor(CONV_ROWS))
+    ref = O.herm(p, ref)
+    err = rel(got, ref)
+    _say("  mixed nonlinear rel err", err)
+    assert err < 1e-5
+    assert 0.0 < c <= dt_rows * (1 + 1e-6)
+    ctx.set_precision("fp64")
+    with pytest.raises(nsc.NscError):
+        ctx.nonlinear(ug)
+    _say("conv full size: FP64 radial solve")
+    Nn = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 92)
+    Nq = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 93)
+    dt, cc = 2e-5, 0.5
+    ctx.set_timestep(dt=dt, c=cc)
+    xg, pg = ctx.radial_solve(ug, Nn.cuda(), Nq.cuda(), pressure=True)
+    torch.cuda.synchronize()
+    m = torch.tensor([a for a, _ in CONV_MODES])
+    kk = torch.tensor([b for _, b in CONV_MODES])
+    gx = xg[:, :, m.cuda(), kk.cuda()].cpu()
+    gp = pg[:, m.cuda(), kk.cuda()].cpu()
+    del xg, pg
+    mirror = torch.where(m == 0, p.M_z - 1 - kk, kk)
+    X, P = O.radial_solve_modes(p, m, kk, u[:, :, m, kk], Nn[:, :, m, kk], Nq[:, :, m, kk], dt, cc)
+    Xm, Pm = O.radial_solve_modes(p, m, mirror, u[:, :, m, mirror], Nn[:, :, m, mirror],
+                                  Nq[:, :, m, mirror], dt, cc)
+    zero = (m == 0)
+    X = torch.where(zero, 0.5 * (X + Xm.conj()), X)
+    P = torch.where(zero, 0.5 * (P + Pm.conj()), P)
+    assert rel(gx, X) < TOL64
+    assert rel(gp, P) < 1e-10
