@@ -691,3 +691,51 @@ def weighted_norm(p, x, r=None, w=None):
     cm[0] = 1.0
     s = ((x.real ** 2 + x.imag ** 2) * cm[None, :, None]).sum(dim=(1, 2))
     return torch.sqrt((w * r * s).sum())
+
+
+# --------------------------------------------------------------------------
+# Restart with a change of resolution (section 2.1: at every restart the
+# spatial resolution may change through interpolation and mode padding;
+# section 2.4: the checkpoint-restart works on the spectral coefficients).
+# Reading (the paper names no interpolant): every Fourier mode's radial
+# profile is carried to the new grid by the polynomial through all points of
+# the old grid; modes present at both resolutions keep their coefficients,
+# new modes start at zero, modes beyond the new truncation are dropped.
+# --------------------------------------------------------------------------
+def lagrange_matrix(x_src, x_dst):
+    """W[i][j] = l_j(x_dst[i]) with the Lagrange basis of the nodes x_src,
+    l_j(x) = prod_{l != j} (x - x_l) / (x_j - x_l), evaluated as written; a
+    new point equal to an old node takes that node's value (W row = e_j)."""
+    x_src = torch.as_tensor(x_src, dtype=F64)
+    x_dst = torch.as_tensor(x_dst, dtype=F64)
+    n0 = x_src.numel()
+    W = torch.zeros(x_dst.numel(), n0, dtype=F64)
+    for i in range(x_dst.numel()):
+        x = x_dst[i]
+        hit = (x_src == x).nonzero()
+        if hit.numel():
+            W[i, int(hit[0])] = 1.0
+            continue
+        for j in range(n0):
+            others = torch.cat([x_src[:j], x_src[j + 1:]])
+            W[i, j] = torch.prod((x - others) / (x_src[j] - others))
+    return W
+
+
+def remap_state(p, u_src, N_r_src):
+    """State u_src [F][N_r_src][M_theta_src][M_z_src] (same geometry eta,
+    L_z) at the resolution of p: modes (m, k) with m < min(M_theta) and
+    |k| <= min(K) copied (k stored at k + K on each side), the others zero;
+    then each mode's profile interpolated from the old radial grid to the
+    new one with lagrange_matrix."""
+    F, n0, mt0, mz0 = u_src.shape
+    assert n0 == N_r_src and F == p.F
+    K0 = (mz0 - 1) // 2
+    mt = min(mt0, p.M_theta)
+    kc = min(K0, p.K)
+    padded = torch.zeros(F, n0, p.M_theta, p.M_z, dtype=C128)
+    for k in range(-kc, kc + 1):
+        padded[:, :, :mt, p.K + k] = u_src[:, :, :mt, K0 + k]
+    src = Params(p.eta, p.Re_i, p.Re_o, p.Ra, p.Pr, n0, p.M_theta, p.M_z, p.L_z)
+    W = lagrange_matrix(radial_grid(src), radial_grid(p)).to(C128)
+    return torch.einsum("ij,fjmk->fimk", W, padded)
