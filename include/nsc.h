@@ -57,12 +57,14 @@ enum {
   NSC_ERR_OOM = -3,       /* device allocation failed or size overflow       */
   NSC_ERR_NONFINITE = -4, /* NaN/Inf detected in a reduction                 */
   NSC_ERR_DT = -5,        /* time step collapsed below 1e-12                 */
-  NSC_ERR_STATE = -6      /* call not valid in the context's current state:
+  NSC_ERR_STATE = -6,     /* call not valid in the context's current state:
                            * also the nonlinear term (and its VJP) at a
                            * precision whose theta line set (all fields of
                            * one (r, z) line, padded, with the twiddles) does
                            * not fit one workgroup's LDS -- FP64 with
                            * N_theta = 1536; the mixed precision fits */
+  NSC_ERR_IO = -7         /* state file missing, unreadable, truncated or
+                           * not a state file                                */
 };
 
 enum { NSC_FP64 = 0, NSC_MIXED = 1 };
@@ -209,6 +211,50 @@ int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
  * the context stream and the host waits for the second event. */
 int nsc_get_timings(nsc_ctx *ctx, double *ms, int n);
 int nsc_set_profiling(nsc_ctx *ctx, int on);
+
+/* Checkpoint-restart on the spectral coefficients, with a change of
+ * resolution at the restart (section 2.1: the resolution may change at every
+ * restart through interpolation and mode padding; section 2.4: the restart
+ * works on the coefficients).
+ *
+ * State file (little endian): a 128-byte header -- char magic[8] =
+ * "NSCSTATE"; uint32 version = 1; uint32 F (3 or 4); int32 N_r, M_theta,
+ * M_z; uint32 zero; FP64 eta, Re_i, Re_o, Ra, Pr, L_z, time; 40 zero bytes --
+ * then the state [F][N_r][M_theta][M_z] as (re, im) FP64 pairs, the layout
+ * of u_hat everywhere in this interface. */
+
+/* Write the DEVICE state u_hat of the context's shape, with the context's
+ * parameters and the given time, to the file at path (created or replaced;
+ * staged through pinned host memory on the context stream, which is
+ * synchronised).  Errors: NSC_ERR_ARG, NSC_ERR_IO, NSC_ERR_DEVICE, NSC_ERR_OOM. */
+int nsc_save_state(nsc_ctx *ctx, const double *u_hat, double time, const char *path);
+
+/* Host only (no device, no context): the header of a state file.  dims: HOST
+ * int[4] = F, N_r, M_theta, M_z; params: HOST double[7] = eta, Re_i, Re_o, Ra,
+ * Pr, L_z, time.  Errors: NSC_ERR_ARG, NSC_ERR_IO (also for a payload whose
+ * size does not match the header). */
+int nsc_read_state_header(const char *path, int *dims, double *params);
+
+/* Read a state file into the DEVICE array u_hat of the context's shape.  The
+ * file's geometry must be the context's (same F, eta and L_z to 1e-12
+ * relative, else NSC_ERR_ARG); its flow parameters may differ (the context's
+ * apply from here on).  At another resolution the state is carried over as
+ * nsc_remap_state does, through a temporary device copy of the file's state.
+ * time_out: NULL or a HOST double receiving the file's time.  Errors:
+ * NSC_ERR_ARG, NSC_ERR_IO, NSC_ERR_DEVICE, NSC_ERR_OOM. */
+int nsc_load_state(nsc_ctx *ctx, const char *path, double *u_hat, double *time_out);
+
+/* Carry a DEVICE state src [F][N_r_src][M_theta_src][M_z_src] of the same
+ * geometry to the context's resolution, into the DEVICE array dst (context
+ * shape; the two must not overlap).  Modes (m, k) present at both
+ * resolutions keep their coefficients, new modes are zero, modes past the
+ * new truncation are dropped; each mode's radial profile is then the value
+ * on the context's grid of the polynomial through the old grid's points
+ * (both grids Chebyshev--Gauss--Lobatto between the walls, whose values are
+ * kept).  N_r_src >= 9, M_theta_src >= 1, M_z_src odd.  Synchronises the
+ * context stream.  Errors: NSC_ERR_ARG, NSC_ERR_DEVICE, NSC_ERR_OOM. */
+int nsc_remap_state(nsc_ctx *ctx, const double *src, int N_r_src, int M_theta_src,
+                    int M_z_src, double *dst);
 
 /* Static description of the status code. */
 const char *nsc_strerror(int status);

@@ -7,8 +7,8 @@ binding: argument marshalling, with PyTorch providing device memory and
 streams.  Importing it loads libnsc.so and fails if it was not built.
 """
 from ._lib import NscError, lib  # noqa: F401
-from .api import Context  # noqa: F401
+from .api import Context, read_state_header  # noqa: F401
 
 lib()  # fail loudly at import when the HIP library is missing
 
-__all__ = ["Context", "NscError", "lib"]
+__all__ = ["Context", "NscError", "lib", "read_state_header"]

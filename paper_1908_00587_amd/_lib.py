@@ -14,6 +14,7 @@ NSC_ERR_OOM = -3
 NSC_ERR_NONFINITE = -4
 NSC_ERR_DT = -5
 NSC_ERR_STATE = -6
+NSC_ERR_IO = -7
 NSC_FP64 = 0
 NSC_MIXED = 1
 
@@ -50,6 +51,10 @@ def _bind(L):
         "nsc_get_grid": ([P, ctypes.POINTER(D), I], I),
         "nsc_get_timings": ([P, ctypes.POINTER(D), I], I),
         "nsc_set_profiling": ([P, I], I),
+        "nsc_save_state": ([P, P, D, ctypes.c_char_p], I),
+        "nsc_read_state_header": ([ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)], I),
+        "nsc_load_state": ([P, ctypes.c_char_p, P, ctypes.POINTER(D)], I),
+        "nsc_remap_state": ([P, P, I, I, I, P], I),
         "nsc_strerror": ([I], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():

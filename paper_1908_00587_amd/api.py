@@ -128,6 +128,40 @@ class Context:
         check(self._L.nsc_step(self._h, _ptr(u), ctypes.byref(d)), "nsc_step")
         return d.value
 
+    # -- checkpoint-restart (section 2.1: resolution change at a restart) ------------
+    def save_state(self, u, path, time=0.0):
+        """Write u (context shape) and the context's parameters to a state file."""
+        _need(u, self.shape, "u")
+        self._sync_stream()
+        check(self._L.nsc_save_state(self._h, _ptr(u), float(time), str(path).encode()),
+              "nsc_save_state")
+
+    def load_state(self, path, out=None):
+        """Read a state file of this geometry, at any resolution, into the
+        context's shape; returns (u, time)."""
+        if out is None:
+            out = self.empty()
+        _need(out, self.shape, "out")
+        t = ctypes.c_double(0.0)
+        self._sync_stream()
+        check(self._L.nsc_load_state(self._h, str(path).encode(), _ptr(out), ctypes.byref(t)),
+              "nsc_load_state")
+        return out, t.value
+
+    def remap_state(self, src, out=None):
+        """A state src [F][N_r'][M_theta'][M_z'] of this geometry carried to the
+        context's resolution (mode padding/truncation, radial interpolation)."""
+        if not (isinstance(src, torch.Tensor) and src.dtype == torch.complex128 and src.is_cuda
+                and src.is_contiguous() and src.dim() == 4 and src.shape[0] == self.F):
+            raise TypeError("src must be a contiguous complex128 CUDA tensor [F][N_r][M_theta][M_z]")
+        if out is None:
+            out = self.empty()
+        _need(out, self.shape, "out")
+        self._sync_stream()
+        check(self._L.nsc_remap_state(self._h, _ptr(src), int(src.shape[1]), int(src.shape[2]),
+                                      int(src.shape[3]), _ptr(out)), "nsc_remap_state")
+        return out
+
     def energy(self, u):
         _need(u, self.shape, "u")
         e = torch.empty(1, dtype=torch.float64, device=self.device)
@@ -154,3 +188,15 @@ class Context:
         buf = (ctypes.c_double * n)()
         check(self._L.nsc_get_timings(self._h, buf, n), "nsc_get_timings")
         return {nm: (buf[i], int(buf[len(names) + i])) for i, nm in enumerate(names)}
+
+
+def read_state_header(path):
+    """Header of a state file (host only): dict with F, N_r, M_theta, M_z, eta,
+    Re_i, Re_o, Ra, Pr, L_z and time."""
+    L = _lib.lib()
+    dims = (ctypes.c_int * 4)()
+    par = (ctypes.c_double * 7)()
+    check(L.nsc_read_state_header(str(path).encode(), dims, par), "nsc_read_state_header")
+    out = dict(zip(("F", "N_r", "M_theta", "M_z"), list(dims)))
+    out.update(zip(("eta", "Re_i", "Re_o", "Ra", "Pr", "L_z", "time"), list(par)))
+    return out

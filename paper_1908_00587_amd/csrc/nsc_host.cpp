@@ -274,6 +274,7 @@ const char *nsc_strerror(int status) {
     case NSC_ERR_NONFINITE: return "non-finite value detected";
     case NSC_ERR_DT: return "time step collapsed below 1e-12";
     case NSC_ERR_STATE: return "call not valid in the current context state";
+    case NSC_ERR_IO: return "state file missing, unreadable, truncated or not a state file";
     default: return "unknown status";
   }
 }

@@ -99,3 +99,54 @@ def test_valid_arguments_reach_the_device_check():
         _lib().nsc_destroy(h)
     else:
         assert st == -2
+
+
+# -- state files: the header reader is host only --------------------------------
+def _write_state(path, F=4, dims=(12, 3, 5), params=(0.71, 100.0, -10.0, 1e4, 0.7, 6.0, 1.25),
+                 magic=b"NSCSTATE", version=1, payload=None):
+    """A state file per the format documented in include/nsc.h, written here
+    independently of the library."""
+    import struct
+    n_r, m_t, m_z = dims
+    head = magic + struct.pack("<II3iI", version, F, n_r, m_t, m_z, 0)
+    head += struct.pack("<7d", *params) + bytes(40)
+    assert len(head) == 128
+    if payload is None:
+        payload = bytes(F * n_r * m_t * m_z * 16)
+    with open(path, "wb") as fh:
+        fh.write(head + payload)
+
+
+def test_state_header_roundtrip(tmp_path):
+    from paper_1908_00587_amd import read_state_header
+    p = tmp_path / "s.nsc"
+    _write_state(p)
+    h = read_state_header(p)
+    assert (h["F"], h["N_r"], h["M_theta"], h["M_z"]) == (4, 12, 3, 5)
+    assert (h["eta"], h["Re_i"], h["Re_o"], h["Ra"], h["Pr"], h["L_z"], h["time"]) == \
+        (0.71, 100.0, -10.0, 1e4, 0.7, 6.0, 1.25)
+
+
+@pytest.mark.parametrize("bad", ["missing", "magic", "version", "truncated", "long", "fields",
+                                 "even_mz", "small_nr"])
+def test_state_header_rejects(tmp_path, bad):
+    from paper_1908_00587_amd import NscError, read_state_header
+    from paper_1908_00587_amd._lib import NSC_ERR_IO
+    p = tmp_path / "s.nsc"
+    if bad == "magic":
+        _write_state(p, magic=b"NSCSTATX")
+    elif bad == "version":
+        _write_state(p, version=2)
+    elif bad == "truncated":
+        _write_state(p, payload=bytes(4 * 12 * 3 * 5 * 16 - 8))
+    elif bad == "long":
+        _write_state(p, payload=bytes(4 * 12 * 3 * 5 * 16 + 16))
+    elif bad == "fields":
+        _write_state(p, F=5, payload=bytes(5 * 12 * 3 * 5 * 16))
+    elif bad == "even_mz":
+        _write_state(p, dims=(12, 3, 4), payload=bytes(4 * 12 * 3 * 4 * 16))
+    elif bad == "small_nr":
+        _write_state(p, dims=(8, 3, 5), payload=bytes(4 * 8 * 3 * 5 * 16))
+    with pytest.raises(NscError) as e:
+        read_state_header(p)
+    assert e.value.code == NSC_ERR_IO
