@@ -194,7 +194,7 @@ def run_gpu(args, wname):
     # dominant kernel and its roofline
     best = None
     for kname, (ms, cnt) in tim.items():
-        if cnt == 0 or kname in ("factor", "cfl"):
+        if cnt == 0 or kname in ("factor", "remap"):
             continue
         if best is None or ms > best[1]:
             best = (kname, ms, cnt)
@@ -267,6 +267,82 @@ def run_cpu(wname, steps):
     return dict(value=steps / el, unit="steps/s", cores=torch.get_num_threads(), kind="oracle",
                 sample=f"{steps} FP64 oracle steps of {wname} (dense LU, DFT matrices), "
                        f"{el:.1f} s")
+
+
+RESTART_FROM = "tc-heated-n64"
+RESTART_TO = (96, 96, 191)  # N_r, M_theta, M_z after the restart
+
+
+def run_restart(reps=20, cpu=True):
+    """Restart with a change of resolution (section 2.1): the heated
+    workload's state carried to N_r = 96 and 96 x 191 modes by the remap
+    kernel (device time from the library's stage timer, HIP events on its
+    stream), the state file written and read back through the local disk,
+    and the oracle's remap of the same state on the host."""
+    import os
+    import tempfile
+
+    import torch
+
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.workloads import amplitudes, params
+
+    args = params(RESTART_FROM)
+    n1, mt1, mz1 = RESTART_TO
+    src = nsc.Context(*args)
+    u = src.initial_state(amplitudes(RESTART_FROM).cuda())
+    ctx = nsc.Context(*args[:5], n1, mt1, mz1, args[8])
+    out = ctx.empty()
+    for _ in range(3):
+        ctx.remap_state(u, out)
+    ctx.timings()
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        ctx.remap_state(u, out)
+    ctx.set_profiling(False)
+    ms, cnt = ctx.timings()["remap"]
+    avg_us = 1e3 * ms / cnt
+    F, n0, mt0, mz0 = u.shape
+    kept = min(mt0, mt1) * (2 * min((mz0 - 1) // 2, (mz1 - 1) // 2) + 1)
+    alg = 16 * F * (n0 * kept + n1 * mt1 * mz1)  # source modes read once, target written once
+    fd, path = tempfile.mkstemp(suffix=".nsc")
+    os.close(fd)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        src.save_state(u, path, time=0.0)
+        t_save = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ctx.load_state(path, out)
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+        fbytes = os.path.getsize(path)
+    finally:
+        os.remove(path)
+    res = {
+        "metric": "restart remap throughput",
+        "value": round(alg / (avg_us * 1e-6) / 1e9, 1), "unit": "GB/s",
+        "workload": f"{RESTART_FROM} -> N_r {n1}, {mt1} x {mz1} modes",
+        "avg_launch_us": round(avg_us, 2), "launches": cnt, "bytes_per_launch": alg,
+        "roofline": {"bound": "hbm", "achieved": round(alg / (avg_us * 1e-6) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "file": {"bytes": fbytes, "save_s": round(t_save, 4), "load_with_remap_s": round(t_load, 4)},
+        "cpu_baseline": None,
+    }
+    if cpu:
+        import oracle as O
+        p0 = O.Params(*args)
+        p1 = O.Params(*args[:5], n1, mt1, mz1, args[8])
+        uc = u.cpu()
+        t0 = time.perf_counter()
+        O.remap_state(p1, uc, n0)
+        el = time.perf_counter() - t0
+        res["cpu_baseline"] = dict(value=round(1.0 / el, 4), unit="remaps/s",
+                                   cores=torch.get_num_threads(), kind="oracle",
+                                   sample=f"one FP64 oracle remap of the same state, {el:.2f} s")
+    return res
 
 
 def _pmc_means(paths):
@@ -378,11 +454,16 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=40)
+    ap.add_argument("--restart", action="store_true",
+                    help="measure the restart remap instead of the time step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a "
               "design, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.restart:
+        print(json.dumps(run_restart(cpu=not args.no_cpu)), flush=True)
+        return
     from paper_1908_00587_amd.workloads import WORKLOADS
     w = WORKLOADS[args.workload]
     g = run_gpu(args, args.workload)

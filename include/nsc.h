@@ -201,7 +201,8 @@ int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
 /* Per-kernel device time accumulated since the last call, in ms (HOST array
  * of n doubles), one entry per kernel: [0] z-inverse (mean profiles, curl,
  * inverse z FFT), [1] theta FFTs + products, [2] forward z FFT (with the
- * CFL reduction when a bound is asked for), [3] unused (kept zero), [4]
+ * CFL reduction when a bound is asked for), [3] restart remap
+ * (nsc_remap_state, and nsc_load_state at another resolution), [4]
  * right sides, [5] Poisson right side (and temperature wall
  * rows), [6] pressure/temperature sweeps, [7] velocity sweeps, [8] influence
  * coefficients, [9] finalisation, [10] factorisation, [11] velocity right

@@ -14,7 +14,7 @@ from ._lib import NSC_FP64, NSC_MIXED, check
 
 
 # kernel order of nsc_get_timings
-KERNELS = ["zinv", "theta", "zfwd", "cfl", "rhs", "div", "sweep_pt", "sweep_vel",
+KERNELS = ["zinv", "theta", "zfwd", "remap", "rhs", "div", "sweep_pt", "sweep_vel",
            "influence", "finalize", "factor", "vel_rhs"]
 
 

@@ -187,10 +187,14 @@ int nsc_remap_state(nsc_ctx *c, const double *src, int N_r_src, int M_theta_src,
   if (hipMalloc((void **)&W_dev, W.size() * sizeof(double)) != hipSuccess) return NSC_ERR_OOM;
   int st = NSC_OK;
   if (hipMemcpyAsync(W_dev, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, c->stream) !=
-          hipSuccess ||
-      nsc::launch_remap(c, src, N_r_src, M_theta_src, M_z_src, W_dev, dst) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess)
+      hipSuccess)
     st = NSC_ERR_DEVICE;
+  if (st == NSC_OK) {
+    nsc::StageTimer t(c, 3);
+    if (nsc::launch_remap(c, src, N_r_src, M_theta_src, M_z_src, W_dev, dst) != hipSuccess)
+      st = NSC_ERR_DEVICE;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess && st == NSC_OK) st = NSC_ERR_DEVICE;
   (void)hipFree(W_dev);
   return st;
 }

@@ -171,27 +171,6 @@ void free_factors(Factors *f) {
   f->vals = f->edge = nullptr;
 }
 
-// ---------------------------------------------------------------------------
-// Stage timing (optional, synchronising)
-// ---------------------------------------------------------------------------
-struct StageTimer {
-  nsc_ctx *c;
-  int stage;
-  StageTimer(nsc_ctx *ctx, int s) : c(ctx), stage(s) {
-    if (c->profiling) (void)hipEventRecord(c->ev0, c->stream);
-  }
-  ~StageTimer() {
-    if (c->profiling) {
-      (void)hipEventRecord(c->ev1, c->stream);
-      (void)hipEventSynchronize(c->ev1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
-      c->stage_ms[stage] += ms;
-      c->stage_cnt[stage] += 1.0;
-    }
-  }
-};
-
 int ensure_factors(nsc_ctx *c, double dt, double cc) {
   if (dt == c->fac_dt && cc == c->fac_c) return NSC_OK;
   StageTimer t(c, 10);

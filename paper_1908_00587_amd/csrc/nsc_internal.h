@@ -124,6 +124,27 @@ struct nsc_ctx {
 
 namespace nsc {
 
+// Stage timing (optional, synchronising): the scope's work on the context
+// stream between two events, accumulated per stage.
+struct StageTimer {
+  nsc_ctx *c;
+  int stage;
+  StageTimer(nsc_ctx *ctx, int s) : c(ctx), stage(s) {
+    if (c->profiling) (void)hipEventRecord(c->ev0, c->stream);
+  }
+  ~StageTimer() {
+    if (c->profiling) {
+      (void)hipEventRecord(c->ev1, c->stream);
+      (void)hipEventSynchronize(c->ev1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+      c->stage_ms[stage] += ms;
+      c->stage_cnt[stage] += 1.0;
+    }
+  }
+};
+
+
 // ---- launchers (kernels in *.hip) -----------------------------------------
 hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u);
 hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl);
