@@ -24,5 +24,5 @@ from .tc import (  # noqa: F401
     nonlinear_planes_direct,
     l_operator, radial_solve, radial_solve_modes, step, next_dt, run,
     energy, base_state, initial_state, cfl_dt, weighted_norm,
-    lagrange_matrix, remap_state,
+    lagrange_matrix, remap_state, diagnostics, probe,
 )

@@ -739,3 +739,47 @@ def remap_state(p, u_src, N_r_src):
     src = Params(p.eta, p.Re_i, p.Re_o, p.Ra, p.Pr, n0, p.M_theta, p.M_z, p.L_z)
     W = lagrange_matrix(radial_grid(src), radial_grid(p)).to(C128)
     return torch.einsum("ij,fjmk->fimk", W, padded)
+
+
+# --------------------------------------------------------------------------
+# Heated-flow diagnostics (section 3: the Nusselt number at the inner
+# cylinder -- the heat transfer there over that of the basic state at the
+# same temperature difference -- and a velocity probe time series).
+# Readings: the heat transfer is the radial derivative of the theta-z mean
+# temperature (mode (0,0)) with the nine-point stencil at the wall; the basic
+# state's is dT_c/dr = 1/(r ln eta).  The torque (not defined in the paper)
+# is the angular-momentum flux G(r) = -2 pi L_z r^3 d(<u_theta>/r)/dr at a
+# wall, which Couette flow carries unchanged through the gap (4 pi L_z B).
+# --------------------------------------------------------------------------
+def diagnostics(p, u, D1=None, r=None):
+    """(Nu_i, Nu_o, G_i, G_o): Nusselt numbers at both walls (0 without
+    temperature) and the torques at both walls."""
+    if r is None:
+        r = radial_grid(p)
+    if D1 is None:
+        D1, _ = fd_matrices(p, r)
+    V = u[1, :, 0, p.K].real
+    dV = D1 @ V
+    G = -2.0 * math.pi * p.L_z * r ** 3 * (dV / r - V / r ** 2)
+    if p.heated:
+        T = u[3, :, 0, p.K].real
+        Nu = (D1 @ T) * r * math.log(p.eta)
+        nu_i, nu_o = float(Nu[0]), float(Nu[-1])
+    else:
+        nu_i = nu_o = 0.0
+    return nu_i, nu_o, float(G[0]), float(G[-1])
+
+
+def probe(p, u, rows, theta, z):
+    """Every field at the physical points (r_rows[n], theta[n], z[n]): the
+    Fourier sum sum_k u_0k e^{ik kz z} + 2 Re sum_{m>=1,k} u_mk e^{i(m theta
+    + k kz z)}, written out term by term.  Returns [n][F]."""
+    out = torch.zeros(len(rows), p.F, dtype=F64)
+    m = torch.arange(p.M_theta, dtype=F64)[:, None]
+    k = (torch.arange(p.M_z, dtype=F64) - p.K)[None, :]
+    c = torch.where(m == 0, 1.0, 2.0)
+    for n, (j, th, zz) in enumerate(zip(rows, theta, z)):
+        ph = torch.exp(1j * (m * th + k * p.kz * zz))
+        for f in range(p.F):
+            out[n, f] = (c * u[f, j] * ph).real.sum()
+    return out
