@@ -213,6 +213,26 @@ int nsc_get_grid(nsc_ctx *ctx, double *r_host, int n);
 int nsc_get_timings(nsc_ctx *ctx, double *ms, int n);
 int nsc_set_profiling(nsc_ctx *ctx, int on);
 
+/* Heated-flow diagnostics (section 3: the Nusselt number at the inner
+ * cylinder, the heat transfer there over that of the basic state at the same
+ * temperature difference).  Writes 4 DEVICE doubles to out: Nu_i, Nu_o (the
+ * theta-z mean temperature's radial derivative at r_i, r_o times r ln(eta),
+ * one-sided nine-point stencils; 1 for the conduction profile; 0 without
+ * temperature), then G_i, G_o, the torques -2 pi L_z r^3 d(<u_theta>/r)/dr at
+ * the two walls (4 pi L_z B for Couette flow).  Queued on the context
+ * stream, no synchronisation.  Errors: NSC_ERR_ARG, NSC_ERR_DEVICE. */
+int nsc_diagnostics(nsc_ctx *ctx, const double *u_hat, double *out);
+
+/* Every field at n <= 64 physical points (section 3: probe time series at
+ * fixed points): point i at radial grid row rows[i], azimuth theta[i], axial
+ * position z[i] (HOST arrays, read before the call returns).  out: DEVICE
+ * [n][F] doubles, the Fourier sums sum_k u_0k e^{i k kz z} + 2 Re sum_{m>=1,k}
+ * u_mk e^{i (m theta + k kz z)}, kz = 2 pi / L_z.  Queued on the context
+ * stream.  Errors: NSC_ERR_ARG (n, a row out of range, a non-finite
+ * position), NSC_ERR_DEVICE. */
+int nsc_probe(nsc_ctx *ctx, const double *u_hat, int n, const int *rows, const double *theta,
+              const double *z, double *out);
+
 /* Checkpoint-restart on the spectral coefficients, with a change of
  * resolution at the restart (section 2.1: the resolution may change at every
  * restart through interpolation and mode padding; section 2.4: the restart

@@ -51,6 +51,8 @@ def _bind(L):
         "nsc_get_grid": ([P, ctypes.POINTER(D), I], I),
         "nsc_get_timings": ([P, ctypes.POINTER(D), I], I),
         "nsc_set_profiling": ([P, I], I),
+        "nsc_diagnostics": ([P, P, P], I),
+        "nsc_probe": ([P, P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D), P], I),
         "nsc_save_state": ([P, P, D, ctypes.c_char_p], I),
         "nsc_read_state_header": ([ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)], I),
         "nsc_load_state": ([P, ctypes.c_char_p, P, ctypes.POINTER(D)], I),

@@ -128,6 +128,30 @@ class Context:
         check(self._L.nsc_step(self._h, _ptr(u), ctypes.byref(d)), "nsc_step")
         return d.value
 
+    # -- diagnostics (section 3: Nusselt number, probe series) -----------------------
+    def diagnostics(self, u):
+        """Device tensor [Nu_i, Nu_o, G_i, G_o]: Nusselt numbers (0 without
+        temperature) and torques at the inner and outer walls."""
+        _need(u, self.shape, "u")
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(self._L.nsc_diagnostics(self._h, _ptr(u), _ptr(out)), "nsc_diagnostics")
+        return out
+
+    def probe(self, u, rows, theta, z):
+        """Device tensor [n][F]: every field at the points (r_rows, theta, z)."""
+        _need(u, self.shape, "u")
+        n = len(rows)
+        if not (len(theta) == n and len(z) == n):
+            raise ValueError("rows, theta and z must have the same length")
+        out = torch.empty(n, self.F, dtype=torch.float64, device=self.device)
+        R = (ctypes.c_int * n)(*[int(x) for x in rows])
+        T = (ctypes.c_double * n)(*[float(x) for x in theta])
+        Z = (ctypes.c_double * n)(*[float(x) for x in z])
+        self._sync_stream()
+        check(self._L.nsc_probe(self._h, _ptr(u), n, R, T, Z, _ptr(out)), "nsc_probe")
+        return out
+
     # -- checkpoint-restart (section 2.1: resolution change at a restart) ------------
     def save_state(self, u, path, time=0.0):
         """Write u (context shape) and the context's parameters to a state file."""

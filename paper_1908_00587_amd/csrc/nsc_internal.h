@@ -20,6 +20,7 @@ constexpr int kMaxFFT = 4096;
 constexpr int kFftThreads = 1024;  // launch bound of the FFT kernels
 constexpr int kWaveRegs = 16;      // complex values per lane in a wavefront-scope FFT stage
 constexpr int kNumStages = 12;  // timed kernels (see nsc_get_timings)
+constexpr int kMaxProbes = 64;  // probe points per nsc_probe call
 
 struct FftPlan {
   int n = 0;

@@ -1,0 +1,89 @@
+"""GPU parity of the heated-flow diagnostics (section 3: Nusselt number at the
+inner cylinder, probe time series) through the C ABI against the oracle:
+wall Nusselt numbers and torques of perturbed states, the basic state's
+closed forms at full size, Fourier-sum probes at random points, and the
+argument checks."""
+import math
+import sys
+
+import pytest
+import torch
+
+import oracle as O
+from paper_1908_00587_amd.workloads import params
+from synthetic import direction
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _nsc():
+    import paper_1908_00587_amd as nsc
+    return nsc
+
+
+CASES = {
+    "heated": (0.71, 50.0, 0.0, 2130.0, 0.7, 16, 8, 15, 2 * math.pi),
+    "iso": (0.5, 50.0, -10.0, 0.0, 1.0, 13, 5, 9, 3.0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_diagnostics_match_oracle(case):
+    _say("diagnostics", case)
+    args = CASES[case]
+    p = O.Params(*args)
+    u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 21)
+    ctx = _nsc().Context(*args)
+    got = ctx.diagnostics(u.cuda()).cpu().tolist()
+    want = O.diagnostics(p, u)
+    for a, b in zip(got, want):
+        assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), (got, want)
+
+
+@pytest.mark.parametrize("name", ["tc-heated-n64", "tc-conv-n256"])
+def test_basic_state_closed_forms_full_size(name):
+    """Conduction: Nu = 1 at both walls; Couette flow: torque 4 pi L_z B at
+    both walls (to the nine-point stencil's truncation error)."""
+    _say("basic state", name)
+    args = params(name)
+    p = O.Params(*args)
+    ctx = _nsc().Context(*args)
+    u = O.base_state(p).cuda()
+    nu_i, nu_o, g_i, g_o = ctx.diagnostics(u).cpu().tolist()
+    lam = 4.0 * math.pi * p.L_z * p.B
+    assert abs(nu_i - 1.0) < 1e-11 and abs(nu_o - 1.0) < 1e-11
+    assert abs(g_i - lam) < 1e-11 * abs(lam) and abs(g_o - lam) < 1e-11 * abs(lam)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_probe_matches_oracle(case):
+    _say("probe", case)
+    args = CASES[case]
+    p = O.Params(*args)
+    u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 22)
+    g = torch.Generator().manual_seed(23)
+    n = 64
+    rows = torch.randint(0, p.N_r, (n,), generator=g).tolist()
+    th = (2 * math.pi * torch.rand(n, generator=g, dtype=torch.float64)).tolist()
+    zz = (p.L_z * torch.rand(n, generator=g, dtype=torch.float64)).tolist()
+    got = _nsc().Context(*args).probe(u.cuda(), rows, th, zz).cpu()
+    want = O.probe(p, u, rows, th, zz)
+    assert float((got - want).abs().max() / want.abs().max()) < 1e-12
+
+
+def test_probe_rejects_bad_arguments():
+    nsc = _nsc()
+    from paper_1908_00587_amd._lib import NSC_ERR_ARG
+    args = CASES["iso"]
+    ctx = nsc.Context(*args)
+    u = O.base_state(O.Params(*args)).cuda()
+    for rows, th, zz in [([], [], []), ([0] * 65, [0.0] * 65, [0.0] * 65),
+                         ([13], [0.0], [0.0]), ([-1], [0.0], [0.0]), ([0], [math.nan], [0.0])]:
+        with pytest.raises(nsc.NscError) as e:
+            ctx.probe(u, rows, th, zz)
+        assert e.value.code == NSC_ERR_ARG
