@@ -87,3 +87,22 @@ def test_probe_rejects_bad_arguments():
         with pytest.raises(nsc.NscError) as e:
             ctx.probe(u, rows, th, zz)
         assert e.value.code == NSC_ERR_ARG
+
+
+def test_rayleigh_ramp_chain_short():
+    """The illustrative example's chain of runs (section 3), shortened: the
+    first run starts conductive (Nu_i = 1 to the stencil's error, the
+    disturbance has no mean part), every later run resumes at the time the
+    previous one saved, and the records stay finite."""
+    _say("rayleigh ramp (short)")
+    from paper_1908_00587_amd.scenario import rayleigh_ramp, summary
+    res = rayleigh_ramp(t_each=0.1, every=10)
+    segs = res["segments"]
+    assert [s["Ra"] for s in segs] == [2130.0, 2840.0, 3550.0]
+    first = segs[0]["series"]
+    assert abs(first[0][1] - 1.0) < 1e-9
+    assert all(abs(x[1] - 1.0) < 1e-4 for x in first)
+    for a, b in zip(segs, segs[1:]):
+        assert b["series"][0][0] == a["series"][-1][0]
+    assert all(math.isfinite(v) for s in segs for x in s["series"] for v in x)
+    assert len(summary(res)) == 3
