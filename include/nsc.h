@@ -247,7 +247,8 @@ int nsc_probe(nsc_ctx *ctx, const double *u_hat, int n, const int *rows, const d
 /* Write the DEVICE state u_hat of the context's shape, with the context's
  * parameters and the given time, to the file at path (created or replaced;
  * staged through pinned host memory on the context stream, which is
- * synchronised).  Errors: NSC_ERR_ARG, NSC_ERR_IO, NSC_ERR_DEVICE, NSC_ERR_OOM. */
+ * synchronised; on an error the partial file is removed).  Errors:
+ * NSC_ERR_ARG, NSC_ERR_IO, NSC_ERR_DEVICE, NSC_ERR_OOM. */
 int nsc_save_state(nsc_ctx *ctx, const double *u_hat, double time, const char *path);
 
 /* Host only (no device, no context): the header of a state file.  dims: HOST

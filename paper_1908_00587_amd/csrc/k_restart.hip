@@ -234,6 +234,7 @@ int nsc_save_state(nsc_ctx *c, const double *u_hat, double time, const char *pat
   }
   if (stage) (void)hipHostFree(stage);
   if (std::fclose(fp) != 0 && st == NSC_OK) st = NSC_ERR_IO;
+  if (st != NSC_OK) std::remove(path);  // no partial state file is left behind
   return st;
 }
 
