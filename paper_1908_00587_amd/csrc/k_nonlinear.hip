@@ -268,7 +268,9 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
   const int nr = d.nr;
   const T mU = T(mur), mV = T(mut), mW = T(muz), mOt = T(mean[4 * nr + j]),
           mOz = T(mean[5 * nr + j]), mG = T(mean[6 * nr + j]);
-  double xr = 0.0, xt = 0.0, xz = 0.0;  // running max |u_r|, |u_theta|, |u_z|
+  // running max |u_r|, |u_theta|, |u_z| in the working precision (the FP32
+  // velocities of the mixed path gain nothing from FP64 maxima)
+  T mr = T(0), mt_ = T(0), mz_ = T(0);
   bool bad = false;
   const bool heated = n_in > 6;
   for (int a = gt; a < nt; a += gsz) {
@@ -290,12 +292,11 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
     buf[pa] = {nr_, nth};
     buf[ls + pa] = {nzz, ntt};
     if (want_cfl) {
-      const double aur = fabs((double)ur + mur), aut = fabs((double)ut + mut),
-                   auz = fabs((double)uz + muz);
+      const T aur = fabs(ur + mU), aut = fabs(ut + mV), auz = fabs(uz + mW);
       if (!(isfinite(aur) && isfinite(aut) && isfinite(auz))) bad = true;
-      xr = fmax(xr, aur);
-      xt = fmax(xt, aut);
-      xz = fmax(xz, auz);
+      mr = fmax(mr, aur);
+      mt_ = fmax(mt_, aut);
+      mz_ = fmax(mz_, auz);
     }
   }
   group_sync<WAVE>();
@@ -315,6 +316,7 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
     if (2 * p + 1 < nout) wl[(size_t)(2 * p + 1) * fstride + m] = y;
   }
   if (want_cfl) {
+    double xr = (double)mr, xt = (double)mt_, xz = (double)mz_;
     if (bad) xr = NAN;
     // wavefront reduction (max, NaN-propagating), then across the workgroup
     auto mx = [](double a, double b) { return (isnan(a) || isnan(b)) ? NAN : fmax(a, b); };

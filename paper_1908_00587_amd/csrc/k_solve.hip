@@ -1098,9 +1098,10 @@ __global__ void k_adj_out(Dims d, const double2 *__restrict__ ub, double2 *__res
 }
 
 // lambda_bar_j = sum_r (X_j+ Xbar+ + X_j- Xbar- + i kappa h_j Xbar_z);
-// beta_bar = -A^-T lambda_bar.  Workgroup of 64 modes x 4 row quarters; the
-// quarters' partial sums meet in LDS (fixed order).
-constexpr int kLamModes = 64, kLamParts = 4;
+// beta_bar = -A^-T lambda_bar.  Workgroup of 64 modes x 16 row parts (a few
+// rows per lane, so each lane's loads go out in one round); the parts'
+// partial sums meet in LDS (fixed order).
+constexpr int kLamModes = 64, kLamParts = 16;
 
 __global__ void __launch_bounds__(kLamModes * kLamParts)
 k_adj_lambda(Dims d, Influence I, const double2 *__restrict__ sx, double2 *__restrict__ bbar) {
