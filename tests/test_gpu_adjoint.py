@@ -165,3 +165,40 @@ def test_fused_step_calls_match_composition():
     b = step_vjp(ctx, u, ubar_next, 1, st2)
     torch.cuda.synchronize()
     assert float((a - b).abs().max() / b.abs().max()) < 1e-14
+
+
+def test_rollout_gradient_full_size_largest_workload():
+    """Largest workload (N_r = 256, 512 x 1023 modes, 1536^2 planes; mixed
+    precision, the only one whose theta line sets fit the LDS there): the
+    adjoint at full size on a short schedule (2 steps at a CFL-sized dt,
+    checkpoint every step), gradient vs central differences along one seeded
+    direction.  About 230 GiB of device memory."""
+    _say("FD adjoint, largest workload")
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout, rollout_energy
+    from paper_1908_00587_amd.workloads import amplitudes, params
+    name = "tc-conv-n256"
+    ctx = nsc.Context(*params(name))
+    ctx.set_precision("mixed")
+    amps = amplitudes(name).cuda()
+    u0 = ctx.initial_state(amps)
+    base = ctx.initial_state(0 * amps)
+    pert_norm = float(torch.linalg.vector_norm(u0 - base))
+    del base
+    steps, dt = 2, 1e-6
+    u0.requires_grad_(True)
+    e = rollout_energy(ctx, u0, steps, dt, ckpt_every=1)
+    e.backward()
+    g = u0.grad
+    u0 = u0.detach()
+    torch.cuda.synchronize()
+    _say("  gradient done")
+    d = direction(ctx.F, ctx.N_r, ctx.M_theta, ctx.M_z, 2100).cuda()
+    d = d * (1e-3 * pert_norm / float(torch.linalg.vector_norm(d)))
+    ctx.set_timestep(dt=dt)
+    ep = float(ctx.energy(rollout(ctx, u0 + d, steps, dt)).cpu()[0])
+    em = float(ctx.energy(rollout(ctx, u0 - d, steps, dt)).cpu()[0])
+    fd = (ep - em) / 2.0
+    an = _inner(g, d)
+    _say(f"  fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(fd):.2e}")
+    assert abs(fd - an) <= 1e-4 * abs(fd)
