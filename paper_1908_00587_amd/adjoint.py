@@ -82,11 +82,12 @@ def step_vjp(ctx, u, ubar_next, n_corr=1, stages=None):
     return ubar
 
 
-def step_stages_fused(ctx, u, n_corr=1):
+def step_stages_fused(ctx, u, n_corr=1, u_next=None):
     """step_stages in one library call (nsc_step_stages): returns
-    (stage states [n_corr][...], u^{n+1})."""
+    (stage states [n_corr][...], u^{n+1}); u_next: optional output buffer."""
     stages = torch.empty((max(n_corr, 1),) + tuple(u.shape), dtype=u.dtype, device=u.device)
-    u_next = torch.empty_like(u)
+    if u_next is None:
+        u_next = torch.empty_like(u)
     ctx._sync_stream()
     check(ctx._L.nsc_step_stages(ctx._h, _p(u), _p(stages), _p(u_next)), "nsc_step_stages")
     return stages, u_next
@@ -114,20 +115,32 @@ class RolloutEnergy(torch.autograd.Function):
     """E(u^S), u^{n+1} = Step(u^n), fixed dt; backward by checkpointing every
     `ckpt_every` steps and recomputing each segment once, stage by stage,
     keeping its stage states for the vector--Jacobian products (memory: two
-    states per step of one segment for one corrector)."""
+    states per step of one segment for one corrector).
+
+    For grids whose states are a sizeable part of the device memory:
+    offload=True keeps the checkpoints in pinned host memory, and
+    keep_stages=False keeps only the segment's step states and recomputes
+    each step's stage states just before its VJP (one state per step of a
+    segment, one more forward step per step)."""
 
     @staticmethod
-    def forward(fctx, u0, ctx, steps, dt, ckpt_every, n_corr):
+    def forward(fctx, u0, ctx, steps, dt, ckpt_every, n_corr, offload, keep_stages):
         ctx.set_timestep(dt=dt, n_corr=n_corr)
         ckpts = []
         u = u0.detach().clone()
         for n in range(steps):
             if n % ckpt_every == 0:
-                ckpts.append(u.clone())
+                if offload:
+                    h = torch.empty(u.shape, dtype=u.dtype, pin_memory=True)
+                    h.copy_(u)
+                    ckpts.append(h)
+                else:
+                    ckpts.append(u.clone())
             ctx.step(u, dt)
         e = ctx.energy(u)
         fctx.ctx = ctx
         fctx.steps, fctx.dt, fctx.ckpt_every, fctx.n_corr = steps, dt, ckpt_every, n_corr
+        fctx.keep_stages = keep_stages
         fctx.ckpts = ckpts
         fctx.save_for_backward(u)
         return e
@@ -145,17 +158,29 @@ class RolloutEnergy(torch.autograd.Function):
             # recompute the segment by stages, keeping each step's state and
             # stage states (the same kernels in the same order as ctx.step)
             states, stages = [], []
-            x = fctx.ckpts[s]
+            x = fctx.ckpts[s].to(uS.device)
             for _ in range(n0, n1):
                 states.append(x)
-                st, x = step_stages_fused(ctx, x, fctx.n_corr)
-                stages.append(st)
+                if fctx.keep_stages:
+                    st, x = step_stages_fused(ctx, x, fctx.n_corr)
+                    stages.append(st)
+                else:
+                    x = x.clone()
+                    ctx.step(x, fctx.dt)
+            spare = None if fctx.keep_stages else torch.empty_like(uS)
             for k in range(n1 - n0 - 1, -1, -1):
-                ubar = step_vjp_fused(ctx, states[k], stages[k], ubar)
-                stages[k] = None
-        return ubar, None, None, None, None, None
+                st = stages[k] if fctx.keep_stages else step_stages_fused(
+                    ctx, states[k], fctx.n_corr, u_next=spare)[0]
+                ubar = step_vjp_fused(ctx, states[k], st, ubar)
+                st = None
+                if fctx.keep_stages:
+                    stages[k] = None
+                states[k] = None
+        return ubar, None, None, None, None, None, None, None
 
 
-def rollout_energy(ctx, u0, steps, dt, ckpt_every=20, n_corr=1):
-    """Perturbation kinetic energy after `steps` steps; differentiable in u0."""
-    return RolloutEnergy.apply(u0, ctx, steps, dt, ckpt_every, n_corr)
+def rollout_energy(ctx, u0, steps, dt, ckpt_every=20, n_corr=1, offload=False, keep_stages=True):
+    """Perturbation kinetic energy after `steps` steps; differentiable in u0
+    (offload, keep_stages: memory options of the backward pass, see
+    RolloutEnergy)."""
+    return RolloutEnergy.apply(u0, ctx, steps, dt, ckpt_every, n_corr, offload, keep_stages)

@@ -262,7 +262,7 @@ int nsc_destroy(nsc_ctx *c) {
   if (!c) return NSC_OK;
   void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
                   c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
-                  c->s_lam, c->s_vjp, c->s_u1, c->s_nn, c->s_nq, c->s_tmp, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
+                  c->s_lam, c->s_vjp, c->s_u1, c->s_nn, c->s_nq, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_factors(&c->fv);
@@ -402,7 +402,10 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
     HIPCHK(hipMemcpy(c->tw32_z, z32.data(), z32.size() * sizeof(float), hipMemcpyHostToDevice));
   }
 
-  // workspaces
+  // workspaces; where the FP64 theta pass cannot run (its line set exceeds
+  // the LDS, and the nonlinear calls refuse FP64), the transform
+  // intermediates are sized for FP32 only
+  if (!theta_fits(c, NSC_FP64, 0)) inter /= 2;
   TRY(dmalloc(&c->zbuf, inter * c->n_in));
   TRY(dmalloc(&c->wbuf, inter * c->n_out));
   c->cfl_nblk = d.nz * d.nr;
@@ -418,7 +421,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   TRY(dmalloc((void **)&c->s_u1, field * d.f));
   TRY(dmalloc((void **)&c->s_nn, field * d.f));
   TRY(dmalloc((void **)&c->s_nq, field * d.f));
-  TRY(dmalloc((void **)&c->s_tmp, field * d.f));
+  c->s_tmp = c->s_u1;  // the initial-state scratch: no step runs meanwhile
   TRY(dmalloc((void **)&c->s_adj, field * c->n_in));
   TRY(dmalloc((void **)&c->s_mean, (size_t)8 * n * sizeof(double)));
   HIPCHK(hipHostMalloc((void **)&c->h_pinned, 64, hipHostMallocDefault));

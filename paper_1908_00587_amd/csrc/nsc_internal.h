@@ -110,7 +110,7 @@ struct nsc_ctx {
   double *s_u1 = nullptr;   // [F][N_r][modes] complex intermediate state
   double *s_nn = nullptr;   // [F][N_r][modes] complex N^n
   double *s_nq = nullptr;   // [F][N_r][modes] complex N^q
-  double *s_tmp = nullptr;  // [F][N_r][modes] complex scratch
+  double *s_tmp = nullptr;  // [F][N_r][modes] initial-state scratch (shares s_u1's memory)
   double *s_adj = nullptr;  // [n_in][N_r][modes] complex adjoint of the derived fields
   double *s_mean = nullptr;  // [8][N_r] mean-flow profiles of the current nonlinear call
   double *h_pinned = nullptr;  // pinned host scalar(s)

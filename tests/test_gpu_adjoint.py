@@ -202,3 +202,77 @@ def test_rollout_gradient_full_size_largest_workload():
     an = _inner(g, d)
     _say(f"  fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(fd):.2e}")
     assert abs(fd - an) <= 1e-4 * abs(fd)
+
+
+@pytest.mark.parametrize("case", ["heated"])
+def test_memory_options_give_the_same_gradient(case):
+    """Checkpoints in pinned host memory and stage states recomputed per step
+    (the memory options of the backward pass) run the same kernels in the
+    same order: the gradient is bit for bit the default one."""
+    _say("adjoint memory options", case)
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout_energy
+    args = CASES[case]
+    p = O.Params(*args)
+    u0 = (O.base_state(p) + 1e-3 * direction(p.F, p.N_r, p.M_theta, p.M_z, 31)).cuda()
+    ctx = nsc.Context(*args)
+    grads = []
+    for offload, keep in [(False, True), (True, False)]:
+        y = u0.clone().requires_grad_(True)
+        rollout_energy(ctx, y, 7, 1e-3, ckpt_every=3, offload=offload, keep_stages=keep).backward()
+        grads.append(y.grad.cpu())
+    assert torch.equal(grads[0], grads[1])
+
+
+def test_largest_workload_full_adjoint_schedule():
+    """The largest workload's schedule on one GPU: 100 mixed-precision steps,
+    the gradient of the final perturbation energy over the last 50 of them
+    with a checkpoint every 10, with the backward pass's memory options
+    (checkpoints in pinned host memory, stage states recomputed per step);
+    checked against central differences along one seeded direction.  Prints
+    the adjoint/forward cost ratio and the device memory in use."""
+    _say("largest workload, full adjoint schedule")
+    import time
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout, rollout_energy
+    from paper_1908_00587_amd.workloads import amplitudes, params
+    name = "tc-conv-n256"
+    ctx = nsc.Context(*params(name))
+    ctx.set_precision("mixed")
+    amps = amplitudes(name).cuda()
+    u = ctx.initial_state(amps)
+    base = ctx.initial_state(0 * amps)
+    pert_norm = float(torch.linalg.vector_norm(u - base))
+    del base
+    dt = 2e-6  # fixed schedule; the initial state's CFL bound is 4.1e-6
+    ctx.set_timestep(dt=dt)
+    for _ in range(50):
+        ctx.step(u, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u50 = u.clone()
+    u = rollout(ctx, u50, 50, dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del u
+    y = u50.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    e = rollout_energy(ctx, y, 50, dt, ckpt_every=10, offload=True, keep_stages=False)
+    e.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    free, total = torch.cuda.mem_get_info()
+    _say(f"  forward {t_fwd:.2f} s, energy + gradient {t_all:.2f} s, ratio {t_all / t_fwd:.2f}; "
+         f"torch peak {torch.cuda.max_memory_allocated() / 2**30:.1f} GiB, "
+         f"in use now {(total - free) / 2**30:.1f} of {total / 2**30:.1f} GiB")
+    g = y.grad
+    del y, e
+    d = direction(ctx.F, ctx.N_r, ctx.M_theta, ctx.M_z, 2101).cuda()
+    d = d * (1e-3 * pert_norm / float(torch.linalg.vector_norm(d)))
+    ctx.set_timestep(dt=dt)
+    ep = float(ctx.energy(rollout(ctx, u50 + d, 50, dt)).cpu()[0])
+    em = float(ctx.energy(rollout(ctx, u50 - d, 50, dt)).cpu()[0])
+    fd = (ep - em) / 2.0
+    an = _inner(g, d)
+    _say(f"  fd {fd:.12e} adjoint {an:.12e} rel {abs(fd - an) / abs(fd):.2e}")
+    assert abs(fd - an) <= 1e-4 * abs(fd)
