@@ -393,10 +393,10 @@ __global__ void __launch_bounds__(64) k_influence_a(Dims d, Grid g, Influence I)
 // memory-bound kernel moderate.
 __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__restrict__ u,
                       const double2 *__restrict__ nn, const double2 *__restrict__ nq,
-                      double2 *__restrict__ sf, double idt, double cc) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int part = blockIdx.z;
+                      double2 *__restrict__ sf, double idt, double cc, int rows_first) {
+  int bx, j, part;
+  stencil_block(rows_first, bx, j, part);
+  const int md = bx * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
@@ -693,9 +693,10 @@ k_sweep(Dims d, SweepArgs a) {
 // Velocity right sides in place of f: f_X - (grad p0)_X inside, wall values
 // on rows 0 and N-1; mode (0,0) solves u_theta directly (X+- = +-i u_theta).
 __global__ void k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ sp,
-                          int walls) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
+                          int walls, int rows_first) {
+  int bx, j, unused;
+  stencil_block(rows_first, bx, j, unused);
+  const int md = bx * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
@@ -737,9 +738,10 @@ __global__ void k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double
 // (0,0), zero elsewhere; all zero for walls = 0) in the same pass.
 __global__ void k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
                        const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc,
-                       int want_p, int walls) {
-  const int md = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
+                       int want_p, int walls, int rows_first) {
+  int bx, j, unused;
+  stencil_block(rows_first, bx, j, unused);
+  const int md = bx * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
@@ -1635,7 +1637,7 @@ hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const
                      c->d, c->g,
                      reinterpret_cast<const double2 *>(u), reinterpret_cast<const double2 *>(nn),
                      reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_f),
-                     1.0 / dt, cc);
+                     1.0 / dt, cc, c->rows_first);
   return hipGetLastError();
 }
 
@@ -1777,7 +1779,7 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   if (stage == 0) {
     hipLaunchKernelGGL(k_div2, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sg,
                        reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
-                       cc, wp, walls);
+                       cc, wp, walls, c->rows_first);
   } else if (stage == 1) {
     // pressure (s_g -> s_p) and temperature (s_f[3] -> s_x[3]) in one launch
     SweepArgs a{};
@@ -1785,7 +1787,8 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
     if (d.heated) a.s[1] = SweepSys{c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
     launch(a, d.heated ? 2 : 1, std::integral_constant<int, 0>{});
   } else if (stage == 2) {
-    hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls);
+    hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls,
+                       c->rows_first);
   } else {
     SweepArgs av{};
     av.s[0] = SweepSys{c->fv, 1, 0, sf, sx};

@@ -402,6 +402,10 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
     HIPCHK(hipMemcpy(c->tw32_z, z32.data(), z32.size() * sizeof(float), hipMemcpyHostToDevice));
   }
 
+  // stencil kernels: rows first once a nine-row window of three fields'
+  // whole radial rows exceeds an XCD's L2 (4 MB)
+  c->rows_first = (size_t)kStencil * 3 * field / d.nr > ((size_t)4 << 20) ? 1 : 0;
+
   // workspaces; where the FP64 theta pass cannot run (its line set exceeds
   // the LDS, and the nonlinear calls refuse FP64), the transform
   // intermediates are sized for FP32 only

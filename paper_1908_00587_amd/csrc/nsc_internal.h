@@ -81,6 +81,7 @@ struct nsc_ctx {
   int device = 0;
   int lds_max = 64 * 1024;  // dynamic LDS bytes per workgroup (device limit)
   int cu_count = 256;       // compute units
+  int rows_first = 0;       // stencil kernels walk rows first (long radial rows)
   int lds_cu = 160 * 1024;  // LDS bytes per compute unit
   // host copies
   double *h_r = nullptr;
@@ -195,6 +196,32 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
   const int q = G / 8, r = G % 8;
   const int x = w % 8, l = w / 8;
   return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// Logical (x, y, z) block coordinates after the XCD remap with y (the radial
+// row) fastest, then z, then x: each XCD walks the rows of a few mode tiles
+// in order, so the nine-row stencil windows of neighbouring rows stay in its
+// L2 however long a radial row is.
+__device__ __forceinline__ void xcd_rows_first(int &bx, int &by, int &bz) {
+  const int gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const int L = xcd_remap(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), gx * gy * gz);
+  by = L % gy;
+  const int rest = L / gy;
+  bz = rest % gz;
+  bx = rest / gz;
+}
+
+// The stencil kernels' block coordinates: rows first where a nine-row
+// window of whole radial rows would not fit an XCD's L2 (the host decides),
+// else the dispatch order (short rows: the window is L2-resident already).
+__device__ __forceinline__ void stencil_block(int rows_first, int &bx, int &by, int &bz) {
+  if (rows_first) {
+    xcd_rows_first(bx, by, bz);
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    bz = blockIdx.z;
+  }
 }
 
 }  // namespace nsc
