@@ -731,12 +731,17 @@ struct ThetaLaunch {
   size_t shm;
 };
 
-ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize) {
+ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize, bool one_line = false) {
   ThetaLaunch L;
   const size_t line = (size_t)line_len(c->d.nt, esize) * esize;
   const size_t tws = (size_t)c->d.nt * esize;
   const int nsets = c->d.nz * c->d.nr;
-  L.wave = c->plan_t.wave_lines >= 2 && (size_t)nlines * line <= 24 * 1024;
+  // wavefront scope: lines that fit a wavefront's registers two at a time
+  // and a line set of at most 24 KB; one_line: also one line at a time and
+  // any line set the LDS holds (768-point lines: measured faster than the
+  // workgroup-scope stages)
+  L.wave = one_line ? (c->plan_t.wave_lines >= 1 && (size_t)nlines * line + tws <= (size_t)c->lds_max)
+                    : (c->plan_t.wave_lines >= 2 && (size_t)nlines * line <= 24 * 1024);
   if (L.wave) {
     int w = (int)(((size_t)c->lds_max - tws) / ((size_t)nlines * line));
     if (w > 4) w = 4;
@@ -789,7 +794,7 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
 template <typename T>
 hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
   const int npi = (c->n_in + 1) / 2;
-  const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>));
+  const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>), true);
   const double dth = 2.0 * M_PI / c->d.nt;
   const double dzs = c->d.lz / c->d.nz;
   return with_fixed_len(c->d.nt, L.wave, [&](auto nf) {
@@ -882,7 +887,7 @@ hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u) {
 bool theta_fits(const nsc_ctx *c, int prec, int adjoint) {
   const int npi = (c->n_in + 1) / 2;
   const size_t esize = prec == NSC_MIXED ? sizeof(C2<float>) : sizeof(C2<double>);
-  return theta_launch(c, adjoint ? npi + 2 : npi, esize).shm <= (size_t)c->lds_max;
+  return theta_launch(c, adjoint ? npi + 2 : npi, esize, !adjoint).shm <= (size_t)c->lds_max;
 }
 
 hipError_t launch_theta(const nsc_ctx *c, int prec, int want_cfl) {
