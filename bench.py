@@ -79,9 +79,9 @@ def kernel_bytes(name, w, prec):
 # precision, the reported value; 192-point transforms)
 DEVICE_KERNEL_WORKLOAD = "tc-heated-n64"
 DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float, 192>", "theta": "nsc::k_theta<float, true, 192>",
-                 "zfwd": "nsc::k_zfwd<float, 192>", "rhs": "nsc::k_rhs", "div": "nsc::k_div2",
+                 "zfwd": "nsc::k_zfwd<float, 192>", "rhs": "nsc::k_rhs<4>", "div": "nsc::k_div2<2>",
                  "sweep_pt": "nsc::k_sweep<true, 0, 64>", "sweep_vel": "nsc::k_sweep<true, 1, 64>",
-                 "vel_rhs": "nsc::k_vel_rhs", "finalize": "nsc::k_finalize<false>",
+                 "vel_rhs": "nsc::k_vel_rhs<1>", "finalize": "nsc::k_finalize<false>",
                  "influence": "nsc::k_influence"}
 
 

@@ -275,15 +275,6 @@ __device__ __forceinline__ double d1_row(const Grid &g, int j, const double *x, 
   return acc;
 }
 
-__device__ __forceinline__ Cd d1_rowc(const Grid &g, int j, const double2 *x, size_t stride) {
-  const int s = g.s[j];
-  const double *w = g.d1 + j * kStencil;
-  Cd acc = {0.0, 0.0};
-#pragma unroll
-  for (int t = 0; t < kStencil; ++t) acc = fmac(w[t], ld(x + (size_t)(s + t) * stride), acc);
-  return acc;
-}
-
 // Homogeneous responses and inverse influence matrices per (m, |k|), in
 // three passes: the pressure responses p_j (Neumann data e_0, e_{N-1}; do not
 // depend on the step size, computed once), then the six velocity responses
@@ -387,58 +378,131 @@ __global__ void __launch_bounds__(64) k_influence_a(Dims d, Grid g, Influence I)
   I.ainv[3 * ns + op] = A[0][0] / det;
 }
 
+// Nine-point stencil sums over R consecutive rows j0 .. j0+nrow-1 of NF
+// fields (field f at x + f * fstride, rows strided by P), with the weights w
+// ([N_r][9], row j's window starting at s_j): acc[f][jj] = sum_t
+// w[j][t] x_f[s_j + t], summed from the left as a single row would, and
+// cen[f][jj] = x_f[j].  The rows the windows share are read once: R + 8 rows
+// when every window is centred, from the first window's start to the last
+// window's end otherwise.
+template <int R, int NF>
+__device__ __forceinline__ void stencil_rows(const Grid &g, const double *__restrict__ w, int n,
+                                             int j0, int nrow, const double2 *x, size_t fstride,
+                                             size_t P, Cd (&acc)[NF][R], Cd (&cen)[NF][R]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) acc[f][jj] = cen[f][jj] = Cd{0, 0};
+  if (j0 >= 4 && j0 + R - 1 <= n - 5) {
+    // row j0+jj reads rows j0+jj-4 .. j0+jj+4
+#pragma unroll
+    for (int rr = 0; rr < R + kStencil - 1; ++rr) {
+      const size_t r = (size_t)(j0 - 4 + rr);
+      Cd xv[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) xv[f] = ld(x + f * fstride + r * P);
+#pragma unroll
+      for (int jj = 0; jj < R; ++jj) {
+        const int t = rr - jj;
+        if (t >= 0 && t < kStencil) {
+          const double wt = w[(j0 + jj) * kStencil + t];
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f][jj] = fmac(wt, xv[f], acc[f][jj]);
+        }
+        if (t == 4)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) cen[f][jj] = xv[f];
+      }
+    }
+  } else {
+    const int lo = g.s[j0];
+    const int hi = g.s[j0 + nrow - 1] + kStencil;
+    for (int r = lo; r < hi; ++r) {
+      Cd xv[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) xv[f] = ld(x + f * fstride + (size_t)r * P);
+#pragma unroll
+      for (int jj = 0; jj < R; ++jj) {
+        const int j = j0 + jj;
+        if (jj < nrow) {
+          const int t = r - g.s[j];
+          if (t >= 0 && t < kStencil) {
+            const double wt = w[j * kStencil + t];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f][jj] = fmac(wt, xv[f], acc[f][jj]);
+          }
+          if (r == j)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) cen[f][jj] = xv[f];
+        }
+      }
+    }
+  }
+}
+
 // f_X = X^n/dt + (1-c) L_q X^n + c N^q + (1-c) N^n for X in {+, -, z, T}.
 // blockIdx.z: 0 the +- pair (from u_r, u_theta), 1 u_z, 2 T -- one stencil
 // family per thread keeps the registers (and so the occupancy) of a
-// memory-bound kernel moderate.
+// memory-bound kernel moderate.  blockIdx.y: a chunk of R rows per lane.
+template <int R>
 __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__restrict__ u,
                       const double2 *__restrict__ nn, const double2 *__restrict__ nq,
                       double2 *__restrict__ sf, double idt, double cc, int rows_first) {
-  int bx, j, part;
-  stencil_block(rows_first, bx, j, part);
+  int bx, cy, part;
+  stencil_block(rows_first, bx, cy, part);
   const int md = bx * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
+  const int j0 = cy * R;
+  const int nrow = n - j0 < R ? n - j0 : R;
   const int m = md / d.mz;
   const int kk = md - m * d.mz;
   const double kap = (double)(kk - d.kmax) * d.kz;
-  const double ri = g.rinv[j];
-  const int s = g.s[j];
-  const double *lw = g.lw + j * kStencil;
   const double ce = 1.0 - cc;
-  const double k2 = kap * kap, r2 = ri * ri;
-  auto U = [&](int f, int row) { return ld(u + ((size_t)f * n + row) * P + md); };
-  // stencil sum of (D2 + D1/r) applied to field f
-  auto L = [&](int f) {
-    Cd acc = {0, 0};
-#pragma unroll
-    for (int t = 0; t < kStencil; ++t) acc = fmac(lw[t], U(f, s + t), acc);
-    return acc;
-  };
-  auto N = [&](int f) -> Cd {
+  const double k2 = kap * kap;
+  const size_t fs = (size_t)n * P;  // field stride
+  auto N = [&](int f, int j) -> Cd {
     if (!nn) return Cd{0, 0};
     const size_t o = ((size_t)f * n + j) * P + md;
     return cc * ld(nq + o) + ce * ld(nn + o);
   };
   if (part == 0) {
-    const Cd lr = L(0), lt = L(1);
-    const Cd ur = U(0, j), ut = U(1, j);
-    const Cd xp = ur + ci(ut), xm = ur - ci(ut);
-    const Cd lp = lr + ci(lt), lm = lr - ci(lt);
+    // stencil sums of (D2 + D1/r) applied to u_r and u_theta
+    Cd l[2][R], x[2][R];
+    stencil_rows<R, 2>(g, g.lw, n, j0, nrow, u + md, fs, P, l, x);
     const double qp = (double)(m + 1), qm = (double)(m >= 1 ? m - 1 : 1 - m);
-    const Cd Lp = lp - (qp * qp * r2 + k2) * xp;
-    const Cd Lm = lm - (qm * qm * r2 + k2) * xm;
-    const Cd a = N(0), b = N(1);
-    st(sf + ((size_t)0 * n + j) * P + md, idt * xp + ce * Lp + (a + ci(b)));
-    st(sf + ((size_t)1 * n + j) * P + md, idt * xm + ce * Lm + (a - ci(b)));
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+      if (jj >= nrow) break;
+      const int j = j0 + jj;
+      const double ri = g.rinv[j];
+      const double r2 = ri * ri;
+      const Cd lr = l[0][jj], lt = l[1][jj];
+      const Cd ur = x[0][jj], ut = x[1][jj];
+      const Cd xp = ur + ci(ut), xm = ur - ci(ut);
+      const Cd lp = lr + ci(lt), lm = lr - ci(lt);
+      const Cd Lp = lp - (qp * qp * r2 + k2) * xp;
+      const Cd Lm = lm - (qm * qm * r2 + k2) * xm;
+      const Cd a = N(0, j), b = N(1, j);
+      st(sf + ((size_t)0 * n + j) * P + md, idt * xp + ce * Lp + (a + ci(b)));
+      st(sf + ((size_t)1 * n + j) * P + md, idt * xm + ce * Lm + (a - ci(b)));
+    }
   } else {
     // u_z (operator L_m) or T (L_m / Pr)
     const int f = part + 1;
-    const Cd x = U(f, j);
-    const Cd Lx = L(f) - ((double)m * (double)m * r2 + k2) * x;
+    Cd l[1][R], x[1][R];
+    stencil_rows<R, 1>(g, g.lw, n, j0, nrow, u + f * fs + md, fs, P, l, x);
     const double cf = f == 3 ? ce / d.pr : ce;
-    st(sf + ((size_t)f * n + j) * P + md, idt * x + cf * Lx + N(f));
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+      if (jj >= nrow) break;
+      const int j = j0 + jj;
+      const double ri = g.rinv[j];
+      const double r2 = ri * ri;
+      const Cd Lx = l[0][jj] - ((double)m * (double)m * r2 + k2) * x[0][jj];
+      st(sf + ((size_t)f * n + j) * P + md, idt * x[0][jj] + cf * Lx + N(f, j));
+    }
   }
 }
 
@@ -692,57 +756,75 @@ k_sweep(Dims d, SweepArgs a) {
 
 // Velocity right sides in place of f: f_X - (grad p0)_X inside, wall values
 // on rows 0 and N-1; mode (0,0) solves u_theta directly (X+- = +-i u_theta).
-__global__ void k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ sp,
-                          int walls, int rows_first) {
-  int bx, j, unused;
-  stencil_block(rows_first, bx, j, unused);
+// R consecutive rows per lane (blockIdx.y: the chunk).
+template <int R>
+__global__ void __launch_bounds__(256)
+k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ sp, int walls,
+          int rows_first) {
+  int bx, cy, unused;
+  stencil_block(rows_first, bx, cy, unused);
   const int md = bx * blockDim.x + threadIdx.x;
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
+  const int j0 = cy * R;
+  const int nrow = n - j0 < R ? n - j0 : R;
   const int m = md / d.mz;
   const int kk = md - m * d.mz;
   const bool zero = (md == d.kmax);
-  double2 *fp = sf + (size_t)j * P + md, *fm = sf + ((size_t)n + j) * P + md,
-          *fz = sf + ((size_t)2 * n + j) * P + md;
-  if (j == 0 || j == n - 1) {
+  auto field = [&](int f, int j) { return sf + ((size_t)f * n + j) * P + md; };
+  auto wall_row = [&](int j) {
     Cd wp = {0, 0};
     if (zero && walls) {
       const double re = j == 0 ? d.re_i : d.re_o;
       wp = {0.0, re};
     }
-    st(fp, wp);
-    st(fm, Cd{-wp.x, -wp.y});
-    st(fz, Cd{0, 0});
-    return;
-  }
+    st(field(0, j), wp);
+    st(field(1, j), Cd{-wp.x, -wp.y});
+    st(field(2, j), Cd{0, 0});
+  };
   if (zero) {
-    const Cd h = 0.5 * (ld(fp) - ld(fm));
-    st(fp, h);
-    st(fm, Cd{-h.x, -h.y});
+    for (int jj = 0; jj < nrow; ++jj) {
+      const int j = j0 + jj;
+      if (j == 0 || j == n - 1) {
+        wall_row(j);
+        continue;
+      }
+      const Cd h = 0.5 * (ld(field(0, j)) - ld(field(1, j)));
+      st(field(0, j), h);
+      st(field(1, j), Cd{-h.x, -h.y});
+    }
     return;
   }
   const double kap = (double)(kk - d.kmax) * d.kz;
-  const double2 *p = sp + md;
-  const Cd pj = ld(p + (size_t)j * P);
-  const Cd dp = d1_rowc(g, j, p, P);
-  const Cd mp = (m * g.rinv[j]) * pj;
-  st(fp, ld(fp) - (dp - mp));
-  st(fm, ld(fm) - (dp + mp));
-  st(fz, ld(fz) - kap * ci(pj));
+  Cd dp[1][R], pc[1][R];
+  stencil_rows<R, 1>(g, g.d1, n, j0, nrow, sp + md, 0, P, dp, pc);
+#pragma unroll
+  for (int jj = 0; jj < R; ++jj) {
+    if (jj >= nrow) break;
+    const int j = j0 + jj;
+    if (j == 0 || j == n - 1) {
+      wall_row(j);
+      continue;
+    }
+    const Cd pj = pc[0][jj];
+    const Cd mp = (m * g.rinv[j]) * pj;
+    double2 *fp = field(0, j), *fm = field(1, j), *fz = field(2, j);
+    st(fp, ld(fp) - (dp[0][jj] - mp));
+    st(fm, ld(fm) - (dp[0][jj] + mp));
+    st(fz, ld(fz) - kap * ci(pj));
+  }
 }
 
-// Poisson right side g = mask(div f); for mode (0,0) the mean-head right side
-// (D1 + 1/r) F_r inside, F_r(r_o) at the outer wall (zeros if not requested).
-// Heated: the wall rows of f_T are replaced by the wall values (+-1/2 in
-// (0,0), zero elsewhere; all zero for walls = 0) in the same pass.
-__global__ void k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
-                       const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc,
-                       int want_p, int walls, int rows_first) {
-  int bx, j, unused;
-  stencil_block(rows_first, bx, j, unused);
-  const int md = bx * blockDim.x + threadIdx.x;
-  if (md >= d.nmodes) return;
+// Poisson right side g = mask(div f) at one (mode, row); for mode (0,0) the
+// mean-head right side (D1 + 1/r) F_r inside, F_r(r_o) at the outer wall
+// (zeros if not requested).  Heated: the wall rows of f_T are replaced by the
+// wall values (+-1/2 in (0,0), zero elsewhere; all zero for walls = 0) in the
+// same pass.
+__device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *__restrict__ sf,
+                                        double2 *__restrict__ sg, const double2 *__restrict__ nn,
+                                        const double2 *__restrict__ nq, double cc, int want_p,
+                                        int walls, int md, int j) {
   const size_t P = d.nmodes;
   const int n = d.nr;
   if (d.heated && (j == 0 || j == n - 1)) {
@@ -767,19 +849,51 @@ __global__ void k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__rest
     st(sg + (size_t)j * P + md, r);
     return;
   }
-  if (j == 0 || j == n - 1) {
-    st(sg + (size_t)j * P + md, Cd{0, 0});
+  st(sg + (size_t)j * P + md, Cd{0, 0});  // wall rows of the other modes
+}
+
+// The same over R consecutive rows per lane: the rows of F_+ and F_- that the
+// rows' nine-point windows share are read once (R + 8 rows for R outputs
+// inside, fewer at the walls) instead of nine times, and each derivative
+// still sums its window from the left, as a single row would.
+template <int R>
+__global__ void __launch_bounds__(256)
+k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
+       const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc, int want_p,
+       int walls, int rows_first) {
+  int bx, cy, unused;
+  stencil_block(rows_first, bx, cy, unused);
+  const int md = bx * blockDim.x + threadIdx.x;
+  if (md >= d.nmodes) return;
+  const size_t P = d.nmodes;
+  const int n = d.nr;
+  const int j0 = cy * R;
+  const int nrow = n - j0 < R ? n - j0 : R;
+  if (md == d.kmax) {
+    for (int jj = 0; jj < nrow; ++jj) div_row(d, g, sf, sg, nn, nq, cc, want_p, walls, md, j0 + jj);
     return;
   }
   const int m = md / d.mz;
   const int kk = md - m * d.mz;
   const double kap = (double)(kk - d.kmax) * d.kz;
-  const double ri = g.rinv[j];
-  const double2 *fp = sf + md, *fm = sf + (size_t)n * P + md, *fz = sf + (size_t)2 * n * P + md;
-  const Cd dp = d1_rowc(g, j, fp, P), dm = d1_rowc(g, j, fm, P);
-  const Cd vp = ld(fp + (size_t)j * P), vm = ld(fm + (size_t)j * P), vz = ld(fz + (size_t)j * P);
-  st(sg + (size_t)j * P + md,
-     0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz));
+  const double2 *fz = sf + (size_t)2 * n * P + md;
+  // D1 of F_+ and F_- (fields 0 and 1 of f)
+  Cd dv[2][R], v[2][R];
+  stencil_rows<R, 2>(g, g.d1, n, j0, nrow, sf + md, (size_t)n * P, P, dv, v);
+#pragma unroll
+  for (int jj = 0; jj < R; ++jj) {
+    const int j = j0 + jj;
+    if (jj >= nrow) break;
+    if (j == 0 || j == n - 1) {
+      div_row(d, g, sf, sg, nn, nq, cc, want_p, walls, md, j);
+      continue;
+    }
+    const double ri = g.rinv[j];
+    const Cd vz = ld(fz + (size_t)j * P);
+    const Cd dp = dv[0][jj], dm = dv[1][jj], vp = v[0][jj], vm = v[1][jj];
+    st(sg + (size_t)j * P + md,
+       0.5 * ((dp + ((1.0 + m) * ri) * vp) + (dm + ((1.0 - m) * ri) * vm)) + kap * ci(vz));
+  }
 }
 
 // lambda = -A^-1 beta(X0), beta = divergence at the two walls.
@@ -1588,6 +1702,23 @@ __global__ void k_energy_grad(Dims d, Grid g, const double2 *__restrict__ u, dou
   }
 }
 
+// Rows per lane of a stencil kernel with `parts` workgroups per (mode tile,
+// row chunk): the longest chunk, up to four rows, that still leaves
+// `min_waves` wavefronts per SIMD.  Longer chunks save reads of the shared
+// window rows but cost occupancy.  Measured on 64 rows x 8128 modes and 128 x
+// 130816: the kernels with two stencil fields per lane (divergence, the +-
+// right sides) are fastest down to four wavefronts per SIMD (two and four
+// rows on the first grid, four on the second); the velocity right sides, one
+// stencil field beside six streamed ones, need eight (one row on the first
+// grid, four on the second).
+inline int chunk_rows(const nsc_ctx *c, int parts, int min_waves) {
+  const long waves_row = (long)(c->d.nmodes + 255) / 256 * 4 * parts;
+  const long simds = 4L * c->cu_count;
+  for (int R = 4; R > 1; R /= 2)
+    if (waves_row * ((c->d.nr + R - 1) / R) >= (long)min_waves * simds) return R;
+  return 1;
+}
+
 inline dim3 mode_grid(const nsc_ctx *c, int y, int z = 1) {
   return dim3((c->d.nmodes + 255) / 256, y, z);
 }
@@ -1633,11 +1764,19 @@ hipError_t launch_influence_setup(const nsc_ctx *c) {
 
 hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const double *nq,
                       double dt, double cc) {
-  hipLaunchKernelGGL(k_rhs, mode_grid(c, c->d.nr, c->d.heated ? 3 : 2), dim3(256), 0, c->stream,
-                     c->d, c->g,
-                     reinterpret_cast<const double2 *>(u), reinterpret_cast<const double2 *>(nn),
-                     reinterpret_cast<const double2 *>(nq), reinterpret_cast<double2 *>(c->s_f),
-                     1.0 / dt, cc, c->rows_first);
+  const int parts = c->d.heated ? 3 : 2;
+  auto rhs = [&](auto rows) {
+    constexpr int R = decltype(rows)::value;
+    hipLaunchKernelGGL((k_rhs<R>), mode_grid(c, (c->d.nr + R - 1) / R, parts), dim3(256), 0,
+                       c->stream, c->d, c->g, reinterpret_cast<const double2 *>(u),
+                       reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
+                       reinterpret_cast<double2 *>(c->s_f), 1.0 / dt, cc, c->rows_first);
+  };
+  switch (chunk_rows(c, parts, 4)) {
+    case 4: rhs(std::integral_constant<int, 4>{}); break;
+    case 2: rhs(std::integral_constant<int, 2>{}); break;
+    default: rhs(std::integral_constant<int, 1>{}); break;
+  }
   return hipGetLastError();
 }
 
@@ -1777,9 +1916,17 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   };
   const size_t fld = (size_t)d.nr * d.nmodes;
   if (stage == 0) {
-    hipLaunchKernelGGL(k_div2, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sg,
-                       reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
-                       cc, wp, walls, c->rows_first);
+    auto div = [&](auto rows) {
+      constexpr int R = decltype(rows)::value;
+      hipLaunchKernelGGL((k_div2<R>), mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0, c->stream,
+                         d, c->g, sf, sg, reinterpret_cast<const double2 *>(nn),
+                         reinterpret_cast<const double2 *>(nq), cc, wp, walls, c->rows_first);
+    };
+    switch (chunk_rows(c, 1, 4)) {
+      case 4: div(std::integral_constant<int, 4>{}); break;
+      case 2: div(std::integral_constant<int, 2>{}); break;
+      default: div(std::integral_constant<int, 1>{}); break;
+    }
   } else if (stage == 1) {
     // pressure (s_g -> s_p) and temperature (s_f[3] -> s_x[3]) in one launch
     SweepArgs a{};
@@ -1787,8 +1934,16 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
     if (d.heated) a.s[1] = SweepSys{c->ft, 0, 0, sf + 3 * fld, sx + 3 * fld};
     launch(a, d.heated ? 2 : 1, std::integral_constant<int, 0>{});
   } else if (stage == 2) {
-    hipLaunchKernelGGL(k_vel_rhs, mode_grid(c, d.nr), dim3(256), 0, c->stream, d, c->g, sf, sp, walls,
-                       c->rows_first);
+    auto vel = [&](auto rows) {
+      constexpr int R = decltype(rows)::value;
+      hipLaunchKernelGGL((k_vel_rhs<R>), mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0,
+                         c->stream, d, c->g, sf, sp, walls, c->rows_first);
+    };
+    switch (chunk_rows(c, 1, 8)) {
+      case 4: vel(std::integral_constant<int, 4>{}); break;
+      case 2: vel(std::integral_constant<int, 2>{}); break;
+      default: vel(std::integral_constant<int, 1>{}); break;
+    }
   } else {
     SweepArgs av{};
     av.s[0] = SweepSys{c->fv, 1, 0, sf, sx};

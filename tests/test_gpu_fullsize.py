@@ -6,6 +6,7 @@ transforms of a row are independent of the other rows) and single Fourier
 modes of the implicit stage (the radial systems of a mode are independent of
 the other modes).  The heated workload also takes one full step against the
 oracle's full step."""
+import math
 import sys
 
 import pytest
@@ -62,7 +63,13 @@ def test_nonlinear_full_size_sampled_rows(name, prec, tol):
 
 
 MODES = {"tc-heated-n64": [(0, 63), (0, 10), (0, 116), (1, 63), (1, 0), (17, 80), (63, 126)],
-         "tc-turb-n128": [(0, 255), (0, 3), (0, 507), (2, 255), (100, 400), (255, 0)]}
+         "tc-turb-n128": [(0, 255), (0, 3), (0, 507), (2, 255), (100, 400), (255, 0)],
+         "heated-n63": [(0, 63), (0, 5), (1, 63), (5, 70), (63, 0)]}
+# the heated workload's modes on 63 radial points: the right-side and
+# divergence kernels take several rows per lane there (four and two), with a
+# short last chunk (63 = 15 x 4 + 3) and one-sided windows in the top chunks
+ARGS = {"tc-heated-n64": params("tc-heated-n64"), "tc-turb-n128": params("tc-turb-n128"),
+        "heated-n63": (0.71, 100.0, 0.0, 1.0e4, 0.7, 63, 64, 127, 2 * math.pi)}
 
 
 @pytest.mark.parametrize("name", list(MODES))
@@ -70,12 +77,14 @@ def test_radial_solve_full_size_sampled_modes(name):
     """Two step sizes on one context: the second refactorises the Helmholtz
     operators and re-solves the velocity responses at full size."""
     _say("radial_solve full size", name)
-    p = O.Params(*params(name))
+    import paper_1908_00587_amd as nsc
+    p = O.Params(*ARGS[name])
     u = O.base_state(p) + 1e-2 * direction(p.F, p.N_r, p.M_theta, p.M_z, 82)
     Nn = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 83)
     Nq = 10 * direction(p.F, p.N_r, p.M_theta, p.M_z, 84)
     c = 0.5
-    ctx = _ctx(name)
+    ctx = nsc.Context(*ARGS[name])
+    ctx.set_precision("fp64")
     m = torch.tensor([a for a, _ in MODES[name]])
     kk = torch.tensor([b for _, b in MODES[name]])
     # the m = 0 column is Hermitian-averaged with its mirror (0, -k)
