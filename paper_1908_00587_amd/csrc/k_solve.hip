@@ -989,17 +989,42 @@ __device__ __forceinline__ Vals final_value(const Dims &d, const Influence &I,
 }
 
 template <bool WITH_P>
-__global__ void k_finalize(Dims d, Influence I, const double2 *__restrict__ sx,
-                           const double2 *__restrict__ sp, const double2 *__restrict__ lam,
-                           double2 *__restrict__ out, double2 *__restrict__ pout) {
+__global__ void __launch_bounds__(256)
+k_finalize(Dims d, Influence I, const double2 *__restrict__ sx, const double2 *__restrict__ sp,
+           const double2 *__restrict__ lam, double2 *__restrict__ out,
+           double2 *__restrict__ pout) {
+  constexpr int NV = WITH_P ? 5 : 4;
+  __shared__ Cd xch[NV][256];
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
-  if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const int n = d.nr;
-  Vals v = final_value<WITH_P>(d, I, sx, sp, lam, j, md);
+  Vals v{}, w{};
+  if (d.mz <= (int)blockDim.x && blockIdx.x == 0) {
+    // the whole m = 0 column lies in this workgroup: its lanes take their
+    // mirror mode's values from the lane that computes them, instead of
+    // computing them a second time
+    if (md < d.nmodes) v = final_value<WITH_P>(d, I, sx, sp, lam, j, md);
+    if (md < d.mz) {
+      xch[0][md] = v.ur;
+      xch[1][md] = v.ut;
+      xch[2][md] = v.uz;
+      xch[3][md] = v.T;
+      if (WITH_P) xch[NV - 1][md] = v.p;
+    }
+    __syncthreads();
+    if (md >= d.nmodes) return;
+    if (md < d.mz) {
+      const int mk = d.mz - 1 - md;
+      w = Vals{xch[0][mk], xch[1][mk], xch[2][mk], xch[3][mk],
+               WITH_P ? xch[NV - 1][mk] : Cd{0, 0}};
+    }
+  } else {
+    if (md >= d.nmodes) return;
+    v = final_value<WITH_P>(d, I, sx, sp, lam, j, md);
+    if (md < d.mz) w = final_value<WITH_P>(d, I, sx, sp, lam, j, d.mz - 1 - md);
+  }
   if (md < d.mz) {  // m = 0: Hermitian projection
-    Vals w = final_value<WITH_P>(d, I, sx, sp, lam, j, d.mz - 1 - md);
     auto h = [](Cd a, Cd b) { return Cd{0.5 * (a.x + b.x), 0.5 * (a.y - b.y)}; };
     v.ur = h(v.ur, w.ur);
     v.ut = h(v.ut, w.ut);
