@@ -416,6 +416,11 @@ constexpr int ct_ns(int n, int s) {
   return ns;
 }
 
+// Complex values per lane in a fixed-length stage: kWaveRegs, and 24 for
+// lines past 768 points (a 1536-point line: three radix-8 butterflies or
+// eight radix-3 ones per lane).
+constexpr int ct_wave_regs(int n) { return n > 768 ? 24 : kWaveRegs; }
+
 // Lines one wavefront carries through every stage (the planner's rule).
 constexpr int ct_wave_lines(int n) {
   const CtRadices p = ct_radices(n);
@@ -423,7 +428,7 @@ constexpr int ct_wave_lines(int n) {
   for (int l = 1; l <= 8; ++l) {
     bool ok = true;
     for (int i = 0; i < p.nst; ++i)
-      if ((l * (n / p.r[i]) + 63) / 64 > kWaveRegs / p.r[i]) ok = false;
+      if ((l * (n / p.r[i]) + 63) / 64 > ct_wave_regs(n) / p.r[i]) ok = false;
     if (!ok) break;
     gl = l;
   }
@@ -438,8 +443,8 @@ __device__ __forceinline__ void ct_stages(LdsC2<T> b0, int nl, LdsC2<T> tw, int 
     constexpr int NS = ct_ns(N, S);
     constexpr int PP = 1 << pad_shift<T>();
     constexpr bool AFF = (N / R) % PP == 0 && (NS % PP == 0 || (NS == 1 && PP % R == 0));
-    stage_body<T, R, INV, kWaveRegs / R, false, AFF, true>(b0, nl, N, lds_line<T>(N), NS, tw,
-                                                           lane, 64);
+    stage_body<T, R, INV, ct_wave_regs(N) / R, false, AFF, true>(b0, nl, N, lds_line<T>(N), NS,
+                                                                 tw, lane, 64);
     ct_stages<T, INV, N, S + 1>(b0, nl, tw, lane);
   }
 }

@@ -760,9 +760,10 @@ ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize, bool one_li
 }
 
 // Transform lengths with compile-time kernels (the padded grids of the
-// configured workloads: 3 x 16, 32, 64 and 256 modes); others run the
-// runtime-length stages.  f receives std::integral_constant<int, NF>.
-template <class F>
+// configured workloads: 3 x 16, 32, 64 and 256 modes; with LONG also 3 x 512,
+// whose lines the runtime plan can only transform at workgroup scope); others
+// run the runtime-length stages.  f receives std::integral_constant<int, NF>.
+template <bool LONG = false, class F>
 hipError_t with_fixed_len(int n, bool allow, F f) {
   if (allow) {
     switch (n) {
@@ -773,6 +774,9 @@ hipError_t with_fixed_len(int n, bool allow, F f) {
       default: break;
     }
   }
+  if constexpr (LONG) {
+    if (n == 1536) return f(std::integral_constant<int, 1536>{});
+  }
   return f(std::integral_constant<int, 0>{});
 }
 
@@ -782,7 +786,8 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
-  return with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+  // FP32 1536-point lines: the fixed-length wavefront stages
+  return with_fixed_len<sizeof(T) == 4>(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
     hipLaunchKernelGGL((k_zinv<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
                        c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
                        reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(tw),
@@ -817,7 +822,7 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw,
   const int threads = z_threads(c->plan_z, tm);
   const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
-  return with_fixed_len(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
+  return with_fixed_len<sizeof(T) == 4>(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
     hipLaunchKernelGGL((k_zfwd<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
                        c->d, c->g, c->plan_z, reinterpret_cast<const C2<T> *>(c->wbuf),
                        reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
