@@ -816,11 +816,12 @@ k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ 
   }
 }
 
-// Poisson right side g = mask(div f) at one (mode, row); for mode (0,0) the
-// mean-head right side (D1 + 1/r) F_r inside, F_r(r_o) at the outer wall
-// (zeros if not requested).  Heated: the wall rows of f_T are replaced by the
-// wall values (+-1/2 in (0,0), zero elsewhere; all zero for walls = 0) in the
-// same pass.
+// Poisson right side g = mask(div f) at one (mode, row) where no divergence
+// is formed: every row of mode (0,0), which takes the mean-head right side
+// (D1 + 1/r) F_r inside and F_r(r_o) at the outer wall (zeros if not
+// requested), and the wall rows of the other modes (zero).  Heated: the wall
+// rows of f_T are replaced by the wall values (+-1/2 in (0,0), zero
+// elsewhere; all zero for walls = 0) in the same pass.
 __device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *__restrict__ sf,
                                         double2 *__restrict__ sg, const double2 *__restrict__ nn,
                                         const double2 *__restrict__ nq, double cc, int want_p,
@@ -852,10 +853,11 @@ __device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *_
   st(sg + (size_t)j * P + md, Cd{0, 0});  // wall rows of the other modes
 }
 
-// The same over R consecutive rows per lane: the rows of F_+ and F_- that the
-// rows' nine-point windows share are read once (R + 8 rows for R outputs
-// inside, fewer at the walls) instead of nine times, and each derivative
-// still sums its window from the left, as a single row would.
+// Poisson right side g = mask(div f) = (D1 + (1+m)/r) F_+ / 2 + (D1 + (1-m)/r)
+// F_- / 2 + i kappa F_z over R consecutive rows per lane: the rows of F_+
+// and F_- that the rows' nine-point windows share are read once (R + 8 rows
+// for R outputs inside, fewer at the walls) instead of nine times, and each
+// derivative still sums its window from the left, as a single row would.
 template <int R>
 __global__ void __launch_bounds__(256)
 k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
