@@ -64,12 +64,17 @@ def test_nonlinear_full_size_sampled_rows(name, prec, tol):
 
 MODES = {"tc-heated-n64": [(0, 63), (0, 10), (0, 116), (1, 63), (1, 0), (17, 80), (63, 126)],
          "tc-turb-n128": [(0, 255), (0, 3), (0, 507), (2, 255), (100, 400), (255, 0)],
-         "heated-n63": [(0, 63), (0, 5), (1, 63), (5, 70), (63, 0)]}
-# the heated workload's modes on 63 radial points: the right-side and
-# divergence kernels take several rows per lane there (four and two), with a
-# short last chunk (63 = 15 x 4 + 3) and one-sided windows in the top chunks
+         "heated-n63": [(0, 63), (0, 5), (1, 63), (5, 70), (63, 0)],
+         "counter-n63": [(0, 63), (0, 120), (1, 63), (40, 70), (127, 0), (127, 126)]}
+# 63 radial points, where the stencil kernels take several rows per lane with
+# a short last chunk and one-sided windows in the top chunks: the heated
+# workload's modes (right sides four rows, 63 = 15 x 4 + 3; divergence two;
+# velocity right sides one) and counter-rotating cylinders on 128 x 127 modes
+# (right sides and divergence four rows; velocity right sides two, 63 =
+# 31 x 2 + 1)
 ARGS = {"tc-heated-n64": params("tc-heated-n64"), "tc-turb-n128": params("tc-turb-n128"),
-        "heated-n63": (0.71, 100.0, 0.0, 1.0e4, 0.7, 63, 64, 127, 2 * math.pi)}
+        "heated-n63": (0.71, 100.0, 0.0, 1.0e4, 0.7, 63, 64, 127, 2 * math.pi),
+        "counter-n63": (0.71, 2000.0, -1000.0, 0.0, 1.0, 63, 128, 127, 2 * math.pi)}
 
 
 @pytest.mark.parametrize("name", list(MODES))
