@@ -191,6 +191,21 @@ int nsc_step_stages(nsc_ctx *ctx, const double *u_hat, double *stages, double *u
 int nsc_step_vjp(nsc_ctx *ctx, const double *u_hat, const double *stages,
                  const double *u_bar_next, double *u_bar);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same product as nsc_step_vjp, by the same kernels in the same order, with
+ * its four state-sized adjoint workspaces taken from a static device array
+ * of 128 MiB that the library holds on every device it runs on until the
+ * process ends.  Allocates nothing.  States up to 32 MiB
+ * (F * N_r * M_theta * M_z * 16 bytes) -- larger ones return NSC_ERR_ARG
+ * before any device work.  Every context on a device shares that array, so
+ * calls that overlap on one device (any contexts, any streams) race; the
+ * array keeps the last call's contents and each call clears what it needs.
+ * Same arguments and other errors as nsc_step_vjp; NSC_ERR_DEVICE if the
+ * array's address could not be obtained when the context was created. */
+int nsc_step_vjp_noalloc(nsc_ctx *ctx, const double *u_hat, const double *stages,
+                         const double *u_bar_next, double *u_bar);
+
 /* Gradient of nsc_energy: g = 2 pi L_z w_j r_j c_m (u - U_b) for the
  * velocity fields, 0 for T (c_0 = 1, c_m = 2).  g is written, not added. */
 int nsc_energy_grad(nsc_ctx *ctx, const double *u_hat, double *g);

@@ -47,6 +47,7 @@ def _bind(L):
         "nsc_radial_solve_vjp": ([P, P, P, P, P], I),
         "nsc_step_stages": ([P, P, P, P], I),
         "nsc_step_vjp": ([P, P, P, P, P], I),
+        "nsc_step_vjp_noalloc": ([P, P, P, P, P], I),
         "nsc_energy_grad": ([P, P, P], I),
         "nsc_get_grid": ([P, ctypes.POINTER(D), I], I),
         "nsc_get_timings": ([P, ctypes.POINTER(D), I], I),

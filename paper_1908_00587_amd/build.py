@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnsc.so")
 SOURCES = ["nsc_host.cpp", "k_nonlinear.hip", "k_solve.hip", "k_restart.hip",
-           "k_diag.hip"]
+           "k_diag.hip", "k_noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are kept out of generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -239,6 +239,48 @@ int solve_impl(nsc_ctx *c, const double *un, const double *nn, const double *nq,
 
 }  // namespace
 
+// Argument checks of the step VJP (pure host code, before any device work).
+int nsc::step_vjp_check(const nsc_ctx *c, const double *u, const double *stages,
+                        const double *ubar_next, const double *ubar) {
+  if (!c || !u || !stages || !ubar_next || !ubar) return NSC_ERR_ARG;
+  if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)ubar_next)
+    return NSC_ERR_ARG;
+  const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
+  const int nc = c->n_corr;
+  if (ubar < stages + (size_t)nc * fld && stages < ubar + fld) return NSC_ERR_ARG;
+  if (!theta_fits(c, c->precision, 1)) return NSC_ERR_STATE;
+  return NSC_OK;
+}
+
+// The step VJP's sequence with its four state-sized adjoint workspaces at
+// work (caller-provided: the context's own, or the allocation-free entry
+// point's static device array).
+int nsc::step_vjp_impl(nsc_ctx *c, const double *u, const double *stages,
+                       const double *ubar_next, double *ubar, double *work) {
+  const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
+  const int nc = c->n_corr;
+  double *abar = work, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
+  TRY(ensure_factors(c, c->dt, c->c));
+  HIPCHK(launch_fill_zero(c, ubar, fld));
+  HIPCHK(launch_fill_zero(c, work, 4 * fld));  // abar, bbar and both x buffers
+  const double *xbar = ubar_next;
+  for (int q = nc; q >= 1; --q) {
+    // X^(q+1) = S(u, a, N(X^(q)))
+    if (q != nc) HIPCHK(launch_fill_zero(c, bbar, fld));
+    HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+    double *xn = (xbar == xa) ? xb : xa;
+    if (q != nc) HIPCHK(launch_fill_zero(c, xn, fld));
+    HIPCHK(launch_nonlinear_vjp(c, c->precision, stages + (size_t)(q - 1) * fld, bbar, xn));
+    xbar = xn;
+  }
+  // X^(1) = S(u, a, a)
+  HIPCHK(launch_fill_zero(c, bbar, fld));
+  HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+  HIPCHK(launch_add(c, abar, bbar, fld));
+  HIPCHK(launch_nonlinear_vjp(c, c->precision, u, abar, ubar));
+  return NSC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Public ABI
 // ---------------------------------------------------------------------------
@@ -318,6 +360,7 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return NSC_ERR_DEVICE;
   HIPCHK(hipGetDevice(&c->device));
+  noalloc_setup(c->device);  // the allocation-free entry point's scratch address
   {
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) ==
@@ -595,34 +638,10 @@ int nsc_step_stages(nsc_ctx *c, const double *u, double *stages, double *u_next)
 
 int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double *ubar_next,
                  double *ubar) {
-  if (!c || !u || !stages || !ubar_next || !ubar) return NSC_ERR_ARG;
-  if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)ubar_next)
-    return NSC_ERR_ARG;
+  TRY(step_vjp_check(c, u, stages, ubar_next, ubar));
   const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
-  const int nc = c->n_corr;
-  if (ubar < stages + (size_t)nc * fld && stages < ubar + fld) return NSC_ERR_ARG;
-  if (!theta_fits(c, c->precision, 1)) return NSC_ERR_STATE;
   if (!c->s_vjp) TRY(dmalloc((void **)&c->s_vjp, 4 * fld * sizeof(double)));
-  double *abar = c->s_vjp, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
-  TRY(ensure_factors(c, c->dt, c->c));
-  HIPCHK(launch_fill_zero(c, ubar, fld));
-  HIPCHK(launch_fill_zero(c, c->s_vjp, 4 * fld));  // abar, bbar and both x buffers
-  const double *xbar = ubar_next;
-  for (int q = nc; q >= 1; --q) {
-    // X^(q+1) = S(u, a, N(X^(q)))
-    if (q != nc) HIPCHK(launch_fill_zero(c, bbar, fld));
-    HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
-    double *xn = (xbar == xa) ? xb : xa;
-    if (q != nc) HIPCHK(launch_fill_zero(c, xn, fld));
-    HIPCHK(launch_nonlinear_vjp(c, c->precision, stages + (size_t)(q - 1) * fld, bbar, xn));
-    xbar = xn;
-  }
-  // X^(1) = S(u, a, a)
-  HIPCHK(launch_fill_zero(c, bbar, fld));
-  HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
-  HIPCHK(launch_add(c, abar, bbar, fld));
-  HIPCHK(launch_nonlinear_vjp(c, c->precision, u, abar, ubar));
-  return NSC_OK;
+  return step_vjp_impl(c, u, stages, ubar_next, ubar, c->s_vjp);
 }
 
 int nsc_energy_grad(nsc_ctx *c, const double *u, double *g) {

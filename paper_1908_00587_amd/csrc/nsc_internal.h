@@ -184,6 +184,16 @@ hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout);
 hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, const double *nbar,
                                 double *ubar);
 
+// The step VJP (nsc_step_vjp): argument checks, and its sequence with the
+// four state-sized adjoint workspaces at `work`.
+int step_vjp_check(const nsc_ctx *c, const double *u, const double *stages,
+                   const double *ubar_next, const double *ubar);
+int step_vjp_impl(nsc_ctx *c, const double *u, const double *stages, const double *ubar_next,
+                  double *ubar, double *work);
+// Record the device address of the allocation-free entry point's static
+// scratch array for the current device (called by nsc_init).
+void noalloc_setup(int device);
+
 // operator kinds for launch_factor
 enum { OP_HELMHOLTZ = 0, OP_POISSON = 1, OP_MEAN_PRESSURE = 2 };
 
