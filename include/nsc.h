@@ -69,9 +69,10 @@ enum {
 
 enum { NSC_FP64 = 0, NSC_MIXED = 1 };
 
-/* Create a context for one problem (Motivation, section 1; section 2.1:
- * "a single input file defines all relevant parameters ... at runtime").
- * eta in (0,1); Re_i, Re_o wall speeds; Ra >= 0 (0 = isothermal) and Pr > 0
+/* Create a context for one problem (section 1, the flow between two
+ * independently rotating cylinders; section 2.1, where every parameter of a
+ * run is read once when the run starts, so that these arguments are the
+ * whole description of the problem).  eta in (0,1); Re_i, Re_o wall speeds; Ra >= 0 (0 = isothermal) and Pr > 0
  * if Ra != 0; N_r >= 9 radial points; M_theta >= 1 azimuthal modes with
  * N_theta = 3 M_theta, M_z odd axial modes with N_z = 3 (M_z+1)/2, both
  * padded lengths of the form 2^a 3^b 5^c and <= 4096; L_z > 0 axial period.
@@ -134,11 +135,17 @@ int nsc_radial_solve(nsc_ctx *ctx, const double *u_hat_n,
  * N(X^(q))) (section 2.1).  *dt_inout (HOST pointer): on entry the step
  * size; on return the size for the next step (changed only if dynamic).
  * With dynamic control the call waits for the first nonlinear stage's CFL
- * scalar (the rest of the step stays queued).  Errors: NSC_ERR_NONFINITE,
- * NSC_ERR_DT. */
+ * scalar (the rest of the step stays queued).  Errors: NSC_ERR_NONFINITE
+ * when u^n holds a NaN or infinite value (the first nonlinear stage finds
+ * it) -- with dynamic control in this call; with a fixed step in this call
+ * if that stage has finished when the call returns (the call does not wait
+ * for it), else in the next nsc_step or nsc_step_stages call, which waits
+ * for it first; NSC_ERR_DT. */
 int nsc_step(nsc_ctx *ctx, double *u_hat, double *dt_inout);
 
-/* Perturbation kinetic energy about circular Couette flow,
+/* Perturbation kinetic energy about the basic state (section 3: the flow
+ * whose azimuthal velocity and temperature depend on r only and are known in
+ * closed form; for the velocity that is circular Couette flow),
  * E = 1/2 int |u - U_b|^2 dV, U_b = (0, A r + B/r, 0), with Clenshaw--Curtis
  * weights in r and Parseval in theta, z; deterministic FP64 reduction.
  * e_dev: one device double. */
@@ -174,7 +181,8 @@ int nsc_radial_solve_vjp(nsc_ctx *ctx, const double *u_bar_out,
                          double *u_bar_n, double *n_bar_n, double *n_bar_q);
 
 /* One predictor--corrector step of the size set by nsc_set_timestep (fixed;
- * no CFL bound, no step-size update) from u_hat, keeping the stage states the
+ * no step-size update; NSC_ERR_NONFINITE as for a fixed nsc_step) from
+ * u_hat, keeping the stage states the
  * adjoint needs: stages = X^(1..n_corr) (n_corr consecutive state-sized
  * arrays, written), u_next = u^{n+1} (written).  Same kernels and arithmetic
  * as nsc_step, so the states agree with it bit for bit.  DEVICE arrays;
@@ -206,7 +214,8 @@ int nsc_step_vjp(nsc_ctx *ctx, const double *u_hat, const double *stages,
 int nsc_step_vjp_noalloc(nsc_ctx *ctx, const double *u_hat, const double *stages,
                          const double *u_bar_next, double *u_bar);
 
-/* Gradient of nsc_energy: g = 2 pi L_z w_j r_j c_m (u - U_b) for the
+/* Gradient of nsc_energy (the perturbation energy about the section 3 basic
+ * state) with respect to the state: g = 2 pi L_z w_j r_j c_m (u - U_b) for the
  * velocity fields, 0 for T (c_0 = 1, c_m = 2).  g is written, not added. */
 int nsc_energy_grad(nsc_ctx *ctx, const double *u_hat, double *g);
 

@@ -53,6 +53,63 @@ __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s
 template <typename T>
 __device__ __forceinline__ C2<T> cmul_is(C2<T> a, T s) { return {-s * a.y, s * a.x}; }
 
+// Twiddle tables.  FP64: the values e^{-2 pi i t/n}.  FP32: compensated
+// pairs (hi, lo), hi the FP32 rounding of the value and lo the FP32 rounding
+// of the remainder, so that a product with hi + lo carries the twiddle to
+// about 2^-48 instead of 2^-24; one 16-byte entry per twiddle either way.
+template <typename T>
+struct TwOf {
+  using type = C2<T>;
+};
+struct alignas(16) TwF32 {
+  float x, y, z, w;  // hi.re, hi.im, lo.re, lo.im
+};
+template <>
+struct TwOf<float> {
+  using type = TwF32;
+};
+template <typename T>
+using TwT = typename TwOf<T>::type;
+template <typename T>
+using LdsTw = __attribute__((address_space(3))) TwT<T> *;
+template <typename T>
+__device__ __forceinline__ LdsTw<T> to_lds_tw(const TwT<T> *p) {
+  return (LdsTw<T>)const_cast<TwT<T> *>(p);
+}
+// C2<T> slots of LDS taken by n twiddle entries
+template <typename T>
+__host__ __device__ constexpr int tw_slots(int n) {
+  return n * (int)(sizeof(TwT<T>) / sizeof(C2<T>));
+}
+
+// v * w, w the table entry (conjugated for the inverse transform).  FP32:
+// v * hi + v * lo, the small products first, so the twiddle's own rounding
+// error does not enter the result.
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> twmul(C2<T> v, LdsTw<T> p) {
+  if constexpr (sizeof(T) == 4) {
+    const float hx = p->x, hy = INV ? -p->y : p->y, lx = p->z, ly = INV ? -p->w : p->w;
+    const float cr = fmaf(v.x, lx, -v.y * ly), ci = fmaf(v.x, ly, v.y * lx);
+    return {fmaf(v.x, hx, fmaf(-v.y, hy, cr)), fmaf(v.x, hy, fmaf(v.y, hx, ci))};
+  } else {
+    C2<T> w{p->x, p->y};
+    if (INV) w.y = -w.y;
+    return cmul(v, w);
+  }
+}
+
+// a * s for a constant s of a butterfly: FP32 multiplies by the
+// compensated pair (hi, lo) of the FP64 constant, FP64 by the constant.
+template <typename T>
+__device__ __forceinline__ T kmul(double s, T a) {
+  if constexpr (sizeof(T) == 4) {
+    const float hi = (float)s, lo = (float)(s - (double)hi);
+    return fmaf(hi, a, lo * a);
+  } else {
+    return (T)s * a;
+  }
+}
+
 // Length-R DFT in registers, y_k = sum_n x_n e^{sgn 2 pi i n k / R},
 // sgn = -1 (forward) or +1 (inverse).
 template <typename T, int R, bool INV>
@@ -71,11 +128,12 @@ template <typename T, bool INV>
 struct Dft<T, 3, INV> {
   __device__ __forceinline__ static void run(C2<T> *v) {
     const T s = INV ? T(1) : T(-1);
-    const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+    constexpr double h = 0.86602540378443864676372317075294;  // sqrt(3)/2
     C2<T> a = v[0], b = v[1], c = v[2];
     C2<T> t1 = cadd(b, c);
     C2<T> t2 = {a.x - T(0.5) * t1.x, a.y - T(0.5) * t1.y};
-    C2<T> t3 = cmul_is(cscale(csub(b, c), h), s);
+    const C2<T> bmc = csub(b, c);
+    C2<T> t3 = cmul_is(C2<T>{kmul<T>(h, bmc.x), kmul<T>(h, bmc.y)}, s);
     v[0] = cadd(a, t1);
     v[1] = cadd(t2, t3);
     v[2] = csub(t2, t3);
@@ -100,17 +158,17 @@ template <typename T, bool INV>
 struct Dft<T, 5, INV> {
   __device__ __forceinline__ static void run(C2<T> *v) {
     const T s = INV ? T(1) : T(-1);
-    const T c1 = T(0.30901699437494742410229341718282);   // cos(2 pi/5)
-    const T c2 = T(-0.80901699437494742410229341718282);  // cos(4 pi/5)
-    const T s1 = T(0.95105651629515357211643933337938);   // sin(2 pi/5)
-    const T s2 = T(0.58778525229247312916870595463907);   // sin(4 pi/5)
+    constexpr double c1 = 0.30901699437494742410229341718282;   // cos(2 pi/5)
+    constexpr double c2 = -0.80901699437494742410229341718282;  // cos(4 pi/5)
+    constexpr double s1 = 0.95105651629515357211643933337938;   // sin(2 pi/5)
+    constexpr double s2 = 0.58778525229247312916870595463907;   // sin(4 pi/5)
     C2<T> a = v[0];
     C2<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
     C2<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-    C2<T> r1 = {a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y};
-    C2<T> r2 = {a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y};
-    C2<T> i1 = cmul_is(C2<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, s);
-    C2<T> i2 = cmul_is(C2<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, s);
+    C2<T> r1 = {a.x + kmul<T>(c1, t1.x) + kmul<T>(c2, t2.x), a.y + kmul<T>(c1, t1.y) + kmul<T>(c2, t2.y)};
+    C2<T> r2 = {a.x + kmul<T>(c2, t1.x) + kmul<T>(c1, t2.x), a.y + kmul<T>(c2, t1.y) + kmul<T>(c1, t2.y)};
+    C2<T> i1 = cmul_is(C2<T>{kmul<T>(s1, t3.x) + kmul<T>(s2, t4.x), kmul<T>(s1, t3.y) + kmul<T>(s2, t4.y)}, s);
+    C2<T> i2 = cmul_is(C2<T>{kmul<T>(s2, t3.x) - kmul<T>(s1, t4.x), kmul<T>(s2, t3.y) - kmul<T>(s1, t4.y)}, s);
     v[0] = cadd(a, cadd(t1, t2));
     v[1] = cadd(r1, i1);
     v[4] = csub(r1, i1);
@@ -123,15 +181,15 @@ template <typename T, bool INV>
 struct Dft<T, 8, INV> {
   __device__ __forceinline__ static void run(C2<T> *v) {
     const T s = INV ? T(1) : T(-1);
-    const T q = T(0.70710678118654752440084436210485);
+    constexpr double q = 0.70710678118654752440084436210485;
     C2<T> e[4] = {v[0], v[2], v[4], v[6]};
     C2<T> o[4] = {v[1], v[3], v[5], v[7]};
     Dft<T, 4, INV>::run(e);
     Dft<T, 4, INV>::run(o);
     // twiddles w8^k, w8 = e^{s i pi/4}
-    C2<T> o1 = {q * (o[1].x - s * o[1].y), q * (o[1].y + s * o[1].x)};
+    C2<T> o1 = {kmul<T>(q, o[1].x - s * o[1].y), kmul<T>(q, o[1].y + s * o[1].x)};
     C2<T> o2 = cmul_is(o[2], s);
-    C2<T> o3 = {q * (-o[3].x - s * o[3].y), q * (-o[3].y + s * o[3].x)};
+    C2<T> o3 = {kmul<T>(q, -o[3].x - s * o[3].y), kmul<T>(q, -o[3].y + s * o[3].x)};
     v[0] = cadd(e[0], o[0]);
     v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], o1);
@@ -147,11 +205,17 @@ struct Dft<T, 8, INV> {
 // the strided writes of the early Stockham stages (stride R elements) and the
 // transposed tile accesses spread over the LDS banks.
 template <typename T>
-__host__ __device__ constexpr int pad_shift() { return 3; }
+__host__ __device__ constexpr int pad_shift() { return 3; }  // stage_body's default SH
 template <typename T>
 __device__ __forceinline__ int PD(int i) { return i + (i >> pad_shift<T>()); }
 template <typename T>
 __host__ __device__ constexpr int lds_line(int n) { return n + (n >> pad_shift<T>()) + 1; }
+// The same with a pad period of 2^SH elements (the long lines of the
+// workgroup-scope theta pass use one slot per 32, to fit two line sets)
+template <int SH>
+__device__ __forceinline__ int PDs(int i) { return i + (i >> SH); }
+template <int SH>
+__host__ __device__ constexpr int lds_line_s(int n) { return n + (n >> SH) + 1; }
 
 
 // Logical (x, y, z) block coordinates after the XCD remap.
@@ -181,9 +245,9 @@ __device__ __forceinline__ void xcd_block_zfirst(int &bx, int &by, int &bz) {
   bx = rest / gy;
 }
 
-// Copy the n twiddles of a plan into LDS (caller synchronises).
-template <typename T>
-__device__ __forceinline__ void load_twiddles(C2<T> *dst, const C2<T> *__restrict__ src, int n) {
+// Copy the n twiddle entries of a plan into LDS (caller synchronises).
+template <typename E>
+__device__ __forceinline__ void load_twiddles(E *dst, const E *__restrict__ src, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
@@ -213,10 +277,10 @@ __device__ __forceinline__ bool affine_stage(int n, int R, int ns) {
 // registers between the read and the write phase.  BLOCK: the threads are
 // the workgroup (barriers); otherwise one wavefront (compiler fences only).
 // Requires nlines * n / R <= MW * nthr.
-template <typename T, int R, bool INV, int MW, bool BLOCK, bool AFF, bool CT = false>
+template <typename T, int R, bool INV, int MW, bool BLOCK, bool AFF, bool CT = false,
+          bool SKIPMID = false, int SH = 3>
 __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int ls, int ns,
-                                           LdsC2<T> tw, int tid, int nthr) {
-  constexpr int SH = pad_shift<T>();
+                                           LdsTw<T> tw, int tid, int nthr) {
   const int nb = n / R;
   const int total = nlines * nb;
   const int step = n / (ns * R);
@@ -248,26 +312,22 @@ __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int 
       const int k = pow2 ? (j & (ns - 1)) : (j % ns);
       LdsC2<T> L = buf + line * ls;
       if (AFF) {
-        LdsC2<T> L0 = L + PD<T>(j);
+        LdsC2<T> L0 = L + PDs<SH>(j);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q][r] = lds_ld(L0 + r * nbp);
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = lds_ld(L + PD<T>(j + r * nb));
+        for (int r = 0; r < R; ++r) v[q][r] = lds_ld(L + PDs<SH>(j + r * nb));
       }
       if (ns > 1) {  // the first stage has unit twiddles
         const int ks = k * step;
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C2<T> w = lds_ld(tw + r * ks);
-          if (INV) w.y = -w.y;
-          v[q][r] = cmul(v[q][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[q][r] = twmul<T, INV>(v[q][r], tw + r * ks);
       }
       Dft<T, R, INV>::run(v[q]);
       const int base = (j - k) * R + k;  // (j / ns) ns R + j mod ns
       wl[q] = line * ls;
-      wa[q] = AFF ? PD<T>(base) : base;
+      wa[q] = AFF ? PDs<SH>(base) : base;
     }
   }
   if (BLOCK) __syncthreads();
@@ -276,13 +336,17 @@ __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int 
   for (int q = 0; q < MW; ++q) {
     if (tid + q * nthr < total) {
       LdsC2<T> L = buf + wl[q];
+      // SKIPMID (last radix-3 stage of a forward theta transform): the middle
+      // third of the outputs, the modes the truncation drops, is not stored
       if (AFF) {
         LdsC2<T> W0 = L + wa[q];
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds_st(W0 + r * nsp, v[q][r]);
+        for (int r = 0; r < R; ++r)
+          if (!(SKIPMID && r == 1)) lds_st(W0 + r * nsp, v[q][r]);
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds_st(L + PD<T>(wa[q] + r * ns), v[q][r]);
+        for (int r = 0; r < R; ++r)
+          if (!(SKIPMID && r == 1)) lds_st(L + PDs<SH>(wa[q] + r * ns), v[q][r]);
       }
     }
   }
@@ -294,7 +358,7 @@ __device__ __forceinline__ void stage_body(LdsC2<T> buf, int nlines, int n, int 
 // callers' registers stay free).
 template <typename T, int R, bool INV, int MAXB>
 __device__ __attribute__((noinline)) void fft_stage(LdsC2<T> buf, int nlines, int n, int ls,
-                                                    int ns, LdsC2<T> tw) {
+                                                    int ns, LdsTw<T> tw) {
   if (affine_stage<T>(n, R, ns))
     stage_body<T, R, INV, MAXB, true, true>(buf, nlines, n, ls, ns, tw, (int)threadIdx.x,
                                             (int)blockDim.x);
@@ -309,11 +373,11 @@ __device__ __attribute__((noinline)) void fft_stage(LdsC2<T> buf, int nlines, in
 // MAXB per thread (the host guarantees n / min_radix <= MAXB * blockDim.x).
 template <typename T, bool INV, int MAXB>
 __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
-                          const C2<T> *tw) {
+                          const TwT<T> *tw) {
   const int n = plan.n;
   int gl = (MAXB * (int)blockDim.x * plan.min_radix) / n;
   if (gl < 1) gl = 1;
-  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
+  LdsTw<T> twl = to_lds_tw<T>(tw);
   for (int l0 = 0; l0 < nlines; l0 += gl) {
     const int nl = nlines - l0 < gl ? nlines - l0 : gl;
     LdsC2<T> b0 = to_lds(buf + l0 * ls);
@@ -347,7 +411,7 @@ __device__ void fft_lines(C2<T> *buf, int nlines, int ls, const FftPlan &plan,
 // hoisted across stages and exhausts the registers.
 template <typename T, int R, bool INV>
 __device__ __attribute__((noinline)) void wave_stage(LdsC2<T> buf, int nlines, int n, int ls,
-                                                     int ns, LdsC2<T> tw, int lane) {
+                                                     int ns, LdsTw<T> tw, int lane) {
   constexpr int MW = kWaveRegs / R;
   if (affine_stage<T>(n, R, ns))
     stage_body<T, R, INV, MW, false, true>(buf, nlines, n, ls, ns, tw, lane, 64);
@@ -358,11 +422,11 @@ __device__ __attribute__((noinline)) void wave_stage(LdsC2<T> buf, int nlines, i
 // Transform of `nlines` lines owned by one wavefront, in groups of
 // plan.wave_lines lines.  Forward (e^{-}) or inverse (e^{+}), unnormalised.
 template <typename T, bool INV>
-__device__ void fft_wave(C2<T> *buf, int nlines, int ls, const FftPlan &plan, const C2<T> *tw,
+__device__ void fft_wave(C2<T> *buf, int nlines, int ls, const FftPlan &plan, const TwT<T> *tw,
                          int lane) {
   const int n = plan.n;
   const int gl = plan.wave_lines;
-  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
+  LdsTw<T> twl = to_lds_tw<T>(tw);
   for (int l0 = 0; l0 < nlines; l0 += gl) {
     const int nl = nlines - l0 < gl ? nlines - l0 : gl;
     LdsC2<T> b0 = to_lds(buf + l0 * ls);
@@ -436,7 +500,7 @@ constexpr int ct_wave_lines(int n) {
 }
 
 template <typename T, bool INV, int N, int S>
-__device__ __forceinline__ void ct_stages(LdsC2<T> b0, int nl, LdsC2<T> tw, int lane) {
+__device__ __forceinline__ void ct_stages(LdsC2<T> b0, int nl, LdsTw<T> tw, int lane) {
   constexpr CtRadices P = ct_radices(N);
   if constexpr (S < P.nst) {
     constexpr int R = P.r[S];
@@ -451,14 +515,97 @@ __device__ __forceinline__ void ct_stages(LdsC2<T> b0, int nl, LdsC2<T> tw, int 
 
 // fft_wave for the fixed length N (line stride lds_line<T>(N)).
 template <typename T, bool INV, int N>
-__device__ __forceinline__ void fft_wave_ct(C2<T> *buf, int nlines, const C2<T> *tw, int lane) {
+__device__ __forceinline__ void fft_wave_ct(C2<T> *buf, int nlines, const TwT<T> *tw, int lane) {
   constexpr int GL = ct_wave_lines(N);
   static_assert(GL > 0, "length too long for a wavefront-scope transform");
   constexpr int LS = lds_line<T>(N);
-  LdsC2<T> twl = to_lds(const_cast<C2<T> *>(tw));
+  LdsTw<T> twl = to_lds_tw<T>(tw);
   for (int l0 = 0; l0 < nlines; l0 += GL) {
     const int nl = nlines - l0 < GL ? nlines - l0 : GL;
     ct_stages<T, INV, N, 0>(to_lds(buf + l0 * LS), nl, twl, lane);
+  }
+}
+
+// Radix orders of the fixed lengths n = 3 * 2^a: ORD_PLAN the planner's
+// (powers of two, then radix 3), ORD_3FIRST radix 3 first, then the
+// planner's powers of two.  In a 3-first transform the first stage's
+// butterflies read elements j, j + n/3, j + 2n/3, so the zero third of a
+// Hermitian-extended line (positions M..2M of a 3M-point line) falls on the
+// middle leg of every butterfly.
+enum { ORD_PLAN = 0, ORD_3FIRST = 1 };
+
+constexpr CtRadices ct_order(int n, int ord) {
+  const CtRadices p = ct_radices(n);
+  if (ord == ORD_PLAN) return p;
+  CtRadices q{0, {}};
+  q.r[q.nst++] = 3;
+  bool dropped = false;
+  for (int i = 0; i < p.nst; ++i) {
+    if (p.r[i] == 3 && !dropped) {
+      dropped = true;
+      continue;
+    }
+    q.r[q.nst++] = p.r[i];
+  }
+  return q;
+}
+
+constexpr int ct_ns_ord(int n, int ord, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= ct_order(n, ord).r[i];
+  return ns;
+}
+
+// Stages S.. of the order ORD; SKIP: the last stage, if radix 3, stores only
+// its outer two output thirds.
+template <typename T, bool INV, int N, int ORD, int S, bool SKIP>
+__device__ __forceinline__ void ct_stages_ord(LdsC2<T> b0, int nl, LdsTw<T> tw, int lane) {
+  constexpr CtRadices P = ct_order(N, ORD);
+  if constexpr (S < P.nst) {
+    constexpr int R = P.r[S];
+    constexpr int NS = ct_ns_ord(N, ORD, S);
+    constexpr int PP = 1 << pad_shift<T>();
+    constexpr bool AFF = (N / R) % PP == 0 && (NS % PP == 0 || (NS == 1 && PP % R == 0));
+    constexpr bool SKIPMID = SKIP && S == P.nst - 1 && R == 3;
+    stage_body<T, R, INV, ct_wave_regs(N) / R, false, AFF, true, SKIPMID>(
+        b0, nl, N, lds_line<T>(N), NS, tw, lane, 64);
+    ct_stages_ord<T, INV, N, ORD, S + 1, SKIP>(b0, nl, tw, lane);
+  }
+}
+
+// Stages S0.. of the order ORD over `nlines` lines of one wavefront (line
+// stride lds_line<T>(N)), in groups of the lines a wavefront carries.
+template <typename T, bool INV, int N, int ORD, int S0, bool SKIP>
+__device__ __forceinline__ void fft_wave_ct_ord(C2<T> *buf, int nlines, const TwT<T> *tw,
+                                                int lane) {
+  constexpr int GL = ct_wave_lines(N);
+  static_assert(GL > 0, "length too long for a wavefront-scope transform");
+  constexpr int LS = lds_line<T>(N);
+  LdsTw<T> twl = to_lds_tw<T>(tw);
+  for (int l0 = 0; l0 < nlines; l0 += GL) {
+    const int nl = nlines - l0 < GL ? nlines - l0 : GL;
+    ct_stages_ord<T, INV, N, ORD, S0, SKIP>(to_lds(buf + l0 * LS), nl, twl, lane);
+  }
+}
+
+// Stages S.. of the order ORD over NL lines (stride lds_line_s<SH>(N)) by a
+// group of G threads (tid = 0..G-1) of a workgroup whose groups all run the
+// same stages: each thread holds its ceil(NL N / (R G)) butterflies of a
+// stage in registers between the read and the write phase, which are
+// separated by workgroup barriers.
+template <typename T, bool INV, int N, int ORD, int S, bool SKIP, int NL, int G, int SH>
+__device__ __forceinline__ void ct_stages_grp(LdsC2<T> b0, LdsTw<T> tw, int tid) {
+  constexpr CtRadices P = ct_order(N, ORD);
+  if constexpr (S < P.nst) {
+    constexpr int R = P.r[S];
+    constexpr int NS = ct_ns_ord(N, ORD, S);
+    constexpr int PP = 1 << SH;
+    constexpr bool AFF = (N / R) % PP == 0 && (NS % PP == 0 || (NS == 1 && PP % R == 0));
+    constexpr bool SKIPMID = SKIP && S == P.nst - 1 && R == 3;
+    constexpr int MW = (NL * (N / R) + G - 1) / G;
+    stage_body<T, R, INV, MW, true, AFF, true, SKIPMID, SH>(b0, NL, N, lds_line_s<SH>(N), NS, tw,
+                                                             tid, G);
+    ct_stages_grp<T, INV, N, ORD, S + 1, SKIP, NL, G, SH>(b0, tw, tid);
   }
 }
 
@@ -468,7 +615,7 @@ __device__ __forceinline__ void fft_wave_ct(C2<T> *buf, int nlines, const C2<T> 
 // NF > 0: the line length is the compile-time constant NF.
 template <typename T, bool INV, int MAXB, int NF = 0>
 __device__ __forceinline__ void fft_block(C2<T> *buf, int nl, int ls, const FftPlan &plan,
-                                          const C2<T> *tw) {
+                                          const TwT<T> *tw) {
   if (NF > 0 || plan.wave_lines > 0) {  // (fixed lengths always fit a wavefront)
     const int nw = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
     const int per = (nl + nw - 1) / nw;

@@ -130,11 +130,11 @@ __device__ void mean_row(const Dims &d, const Grid &g, const double2 *__restrict
 
 template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
-                       C2<T> *__restrict__ Z, const C2<T> *__restrict__ tw, int tm, int drop_mean,
+                       C2<T> *__restrict__ Z, const TwT<T> *__restrict__ tw, int tm, int drop_mean,
                        double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nz;
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + d.nz);
   int bx, j, f;
   xcd_block_zfirst(bx, j, f);  // the fields of one tile share their u rows
   const int nz = d.nz, K = d.kmax;
@@ -145,7 +145,10 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   // one workgroup per radial row also records the mean-flow profiles there
   if (bx == 0 && f == 0 && threadIdx.x == 0) mean_row(d, g, u, mean, j);
   // retained modes: one item per (line, k) so that every thread's loads are
-  // independent and issued together; then the zero padding
+  // independent and issued together; then the zero padding.  (A pruned
+  // radix-3-first variant that fed the derived values of the two retained
+  // modes of each butterfly straight into it measured slower on the
+  // 1536-point lines and no faster on the 192-point ones.)
   const int mz = d.mz;
   for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
     const int li = w.r;
@@ -228,7 +231,7 @@ __device__ __forceinline__ void group_sync() {
 
 template <typename T, bool WAVE, bool INV, int NF>
 __device__ __forceinline__ void group_fft(C2<T> *buf, int nl, int ls, const FftPlan &p,
-                                          const C2<T> *tw, int gt) {
+                                          const TwT<T> *tw, int gt) {
   if constexpr (WAVE && NF > 0) fft_wave_ct<T, INV, NF>(buf, nl, tw, gt);
   else if constexpr (WAVE) fft_wave<T, INV>(buf, nl, ls, p, tw, gt);
   else fft_lines<T, INV, kMaxB>(buf, nl, ls, p, tw);
@@ -237,11 +240,11 @@ __device__ __forceinline__ void group_fft(C2<T> *buf, int nl, int ls, const FftP
 template <typename T, bool WAVE, int NF>
 __global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
 k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
-                        C2<T> *__restrict__ W, const C2<T> *__restrict__ tw, int n_in,
+                        C2<T> *__restrict__ W, const TwT<T> *__restrict__ tw, int n_in,
                         double dth, double dzs, double *__restrict__ cfl_part,
                         int want_cfl, const double *__restrict__ mean) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
   __shared__ double red[3 * (kFftThreads / 64)];
   const int nt = d.nt, mt = d.mt;
   const int ls = lds_line<T>(nt);
@@ -252,7 +255,7 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
   __syncthreads();
   if (grp.set >= d.nz * d.nr) return;  // wavefronts past the last set (WAVE only)
   const int j = grp.set / d.nz, b = grp.set - j * d.nz;  // radial row, z index
-  C2<T> *buf = tws + nt + (size_t)grp.slot * npi * ls;
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + nt) + (size_t)grp.slot * npi * ls;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   const C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
   // pack pairs of real fields into Hermitian-extended complex lines: one
@@ -356,6 +359,227 @@ k_theta(Dims d, Grid g, FftPlan pt, const C2<T> *__restrict__ Z,
   }
 }
 
+// Maximum over the wavefront of 32-bit values (DPP row shifts, then the
+// row broadcasts), in every lane.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Theta pass for the fixed lengths N = 3 M (M = M_theta) with NI = 6 or 9
+// derived fields (isothermal, heated).  A group of G threads per (r, z) line
+// set, blockDim.x / G sets per workgroup sharing one twiddle table: G = 64,
+// one wavefront per set, needs no workgroup barrier in the transforms (the
+// short lines, 48..768 points); G > 64 (the long lines) runs each stage at
+// workgroup scope.  LDS lines have one pad slot per 2^SH elements.
+//   * Packing and the first inverse stage are one step: the inverse runs
+//     radix 3 first, whose butterfly q reads positions q, q + M, q + 2M of
+//     the Hermitian-extended line -- Z_q (mode q), zero (the padding), and
+//     Z_{N-(M-q)} (the conjugate half, mode M - q) -- so each thread loads
+//     the two modes from the intermediate array, forms the pruned radix-3
+//     butterfly in registers and writes its three outputs: no zero fill and
+//     no LDS round trip for the packing.
+//   * The forward transform runs radix 3 last and stores only the outer two
+//     thirds of that stage's outputs (modes below M and their mirrors).
+//   * The CFL maxima of the FP32 path are taken on the bit patterns of |u|
+//     (non-negative floats order as unsigned integers, NaN and infinity above
+//     every finite value, so the maximum also flags them), reduced across
+//     each wavefront by DPP.
+template <typename T, int N, int NI, int G, int SH>
+__global__ void __launch_bounds__(1024)
+k_theta_fx(Dims d, Grid g, const C2<T> *__restrict__ Z, C2<T> *__restrict__ W,
+           const TwT<T> *__restrict__ tw, double dth, double dzs, double *__restrict__ cfl_part,
+           int want_cfl, const double *__restrict__ mean) {
+  constexpr int MT = N / 3;
+  constexpr int LS = lds_line_s<SH>(N);
+  constexpr int NP = (NI + 1) / 2;  // packed lines
+  constexpr bool HEATED = NI > 6;
+  constexpr bool WAVE = G == 64;
+  constexpr int NW = G / 64;  // wavefronts per set
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[3][kFftThreads / 64];
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
+  const int sets = (int)blockDim.x / G;
+  const int slot = (int)threadIdx.x / G, tid = (int)threadIdx.x - slot * G;
+  const int nsets = d.nz * d.nr;
+  const int set0 = xcd_remap((int)blockIdx.x, (int)gridDim.x) * sets + slot;
+  const bool valid = set0 < nsets;
+  load_twiddles(tws, tw, N);
+  __syncthreads();
+  if (WAVE && !valid) return;  // wavefronts past the last set (no barrier follows)
+  // a group past the last set (G > 64) repeats the last set's work for the
+  // workgroup barriers, and stores nothing
+  const int set = valid ? set0 : nsets - 1;
+  const int j = set / d.nz, b = set - j * d.nz;  // radial row, z index
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + N) + (size_t)slot * NP * LS;
+  LdsC2<T> bl = to_lds(buf);
+  LdsTw<T> twl = to_lds_tw<T>(tws);
+  const size_t fstride = (size_t)d.nr * d.nz * MT;
+  const C2<T> *zl = Z + ((size_t)j * d.nz + b) * MT;
+  // packing + pruned radix-3 stage (inverse: w = e^{+2 pi i/3}); butterfly
+  // (p, q): a = Z_q, c = Z_{N-(M-q)} (zero for q = 0: mode M is not kept)
+  constexpr double H3 = 0.86602540378443864676372317075294;  // sqrt(3)/2
+#pragma unroll
+  for (int it0 = 0; it0 < NP * MT; it0 += G) {
+    const int it = it0 + tid;
+    if (it < NP * MT) {
+      const int p = it / MT, q = it - p * MT;
+      const C2<T> *f1 = zl + (size_t)(2 * p) * fstride;
+      const bool two = 2 * p + 1 < NI;
+      const C2<T> F1 = f1[q];
+      const C2<T> F2 = two ? f1[fstride + q] : C2<T>{T(0), T(0)};
+      C2<T> a, c{T(0), T(0)};
+      if (q == 0) {
+        a = {F1.x, F2.x};
+      } else {
+        a = {F1.x - F2.y, F1.y + F2.x};
+        const C2<T> G1 = f1[MT - q];
+        const C2<T> G2 = two ? f1[fstride + MT - q] : C2<T>{T(0), T(0)};
+        c = {G1.x + G2.y, G2.x - G1.y};
+      }
+      // y0 = a + c, y1 = a + e^{4 pi i/3} c, y2 = a + e^{2 pi i/3} c
+      const C2<T> t = {a.x - T(0.5) * c.x, a.y - T(0.5) * c.y};
+      const C2<T> hc = {kmul<T>(H3, c.x), kmul<T>(H3, c.y)};
+      LdsC2<T> L = bl + p * LS;
+      lds_st(L + PDs<SH>(3 * q), cadd(a, c));
+      lds_st(L + PDs<SH>(3 * q + 1), C2<T>{t.x + hc.y, t.y - hc.x});
+      lds_st(L + PDs<SH>(3 * q + 2), C2<T>{t.x - hc.y, t.y + hc.x});
+    }
+  }
+  if constexpr (WAVE) {
+    wave_sync();
+    fft_wave_ct_ord<T, true, N, ORD_3FIRST, 1, false>(buf, NP, tws, tid);
+  } else {
+    __syncthreads();
+    ct_stages_grp<T, true, N, ORD_3FIRST, 1, false, NP, G, SH>(bl, twl, tid);
+  }
+  // pointwise products and CFL maxima
+  const int nr = d.nr;
+  const T mU = T(mean[j]), mV = T(mean[nr + j]), mW = T(mean[2 * nr + j]),
+          mOt = T(mean[4 * nr + j]), mOz = T(mean[5 * nr + j]), mG = T(mean[6 * nr + j]);
+  unsigned br = 0, bt = 0, bz = 0;  // FP32: bit patterns of the maxima
+  T mr = T(0), mt_ = T(0), mz_ = T(0);
+  bool bad = false;
+#pragma unroll
+  for (int a0 = 0; a0 < N; a0 += G) {
+    const int a = a0 + tid;
+    if (a < N) {
+      LdsC2<T> P0 = bl + PDs<SH>(a);
+      const C2<T> l0 = lds_ld(P0), l1 = lds_ld(P0 + LS), l2 = lds_ld(P0 + 2 * LS);
+      const T ur = l0.x, ut = l0.y, uz = l1.x, wr = l1.y, wt = l2.x, wz = l2.y;
+      // u' x omega' + U x omega' + u' x Omega (Omega_r = 0); U x Omega is
+      // exact in mode (0,0)
+      const T nr_ = (ut * wz - uz * wt) + (mV * wz - mW * wt) + (ut * mOz - uz * mOt);
+      const T nth = (uz * wr - ur * wz) + (mW * wr - mU * wz) - ur * mOz;
+      const T nzz = (ur * wt - ut * wr) + (mU * wt - mV * wr) + ur * mOt;
+      T ntt = T(0);
+      if constexpr (HEATED) {
+        // -(u' . grad T' + U . grad T' + u_r' dT_m/dr)
+        const C2<T> l3 = lds_ld(P0 + 3 * LS), l4 = lds_ld(P0 + 4 * LS);
+        ntt = -((ur * l3.x + ut * l3.y + uz * l4.x) + (mU * l3.x + mV * l3.y + mW * l4.x) +
+                ur * mG);
+      }
+      lds_st(P0, C2<T>{nr_, nth});
+      lds_st(P0 + LS, C2<T>{nzz, ntt});
+      if (want_cfl) {
+        const T aur = fabs(ur + mU), aut = fabs(ut + mV), auz = fabs(uz + mW);
+        if constexpr (sizeof(T) == 4) {
+          br = max(br, __float_as_uint(aur));
+          bt = max(bt, __float_as_uint(aut));
+          bz = max(bz, __float_as_uint(auz));
+        } else {
+          if (!(isfinite(aur) && isfinite(aut) && isfinite(auz))) bad = true;
+          mr = fmax(mr, aur);
+          mt_ = fmax(mt_, aut);
+          mz_ = fmax(mz_, auz);
+        }
+      }
+    }
+  }
+  if constexpr (WAVE) {
+    wave_sync();
+    fft_wave_ct_ord<T, false, N, ORD_PLAN, 0, true>(buf, 2, tws, tid);
+  } else {
+    __syncthreads();
+    ct_stages_grp<T, false, N, ORD_PLAN, 0, true, 2, G, SH>(bl, twl, tid);
+  }
+  // unpack the two real transforms of each line, keep m < M_theta
+  C2<T> *wl = W + ((size_t)j * d.nz + b) * MT;
+  if (valid) {
+#pragma unroll
+    for (int it0 = 0; it0 < 2 * MT; it0 += G) {
+      const int it = it0 + tid;
+      if (it < 2 * MT) {
+        const int p = it / MT, m = it - p * MT;
+        const C2<T> zm = lds_ld(bl + p * LS + PDs<SH>(m));
+        const C2<T> zc = lds_ld(bl + p * LS + PDs<SH>(m == 0 ? 0 : N - m));
+        // X = (Z_m + conj Z_{-m}) / 2, Y = (Z_m - conj Z_{-m}) / (2 i)
+        wl[(size_t)(2 * p) * fstride + m] = {T(0.5) * (zm.x + zc.x), T(0.5) * (zm.y - zc.y)};
+        if (HEATED || p == 0)
+          wl[(size_t)(2 * p + 1) * fstride + m] = {T(0.5) * (zm.y + zc.y), T(0.5) * (zc.x - zm.x)};
+      }
+    }
+  }
+  if (want_cfl) {
+    // this wavefront's maxima (xr NaN: a value was not finite)
+    double xr, xt, xz;
+    auto mx = [](double u, double v) { return (isnan(u) || isnan(v)) ? NAN : fmax(u, v); };
+    if constexpr (sizeof(T) == 4) {
+      br = wave_max_u32(br);
+      bt = wave_max_u32(bt);
+      bz = wave_max_u32(bz);
+      const unsigned inf = 0x7f800000u;
+      xr = (br >= inf || bt >= inf || bz >= inf) ? (double)NAN : (double)__uint_as_float(br);
+      xt = (double)__uint_as_float(bt);
+      xz = (double)__uint_as_float(bz);
+    } else {
+      xr = (double)mr;
+      xt = (double)mt_;
+      xz = (double)mz_;
+      if (bad) xr = NAN;
+      for (int off = 32; off > 0; off >>= 1) {  // total in lane 0
+        xr = mx(xr, __shfl_down(xr, off, 64));
+        xt = mx(xt, __shfl_down(xt, off, 64));
+        xz = mx(xz, __shfl_down(xz, off, 64));
+      }
+    }
+    if constexpr (!WAVE) {  // across the group's wavefronts
+      const int w = tid >> 6;
+      if ((tid & 63) == 0) {
+        red[0][slot * NW + w] = xr;
+        red[1][slot * NW + w] = xt;
+        red[2][slot * NW + w] = xz;
+      }
+      __syncthreads();
+      xr = red[0][slot * NW];
+      xt = red[1][slot * NW];
+      xz = red[2][slot * NW];
+#pragma unroll
+      for (int k = 1; k < NW; ++k) {
+        xr = mx(xr, red[0][slot * NW + k]);
+        xt = mx(xt, red[1][slot * NW + k]);
+        xz = mx(xz, red[2][slot * NW + k]);
+      }
+    }
+    if (tid == 0 && valid) {
+      double v = DBL_MAX;
+      if (isnan(xr)) {
+        v = NAN;
+      } else {
+        if (xr > 0.0) v = fmin(v, g.dr[j] / xr);
+        if (xt > 0.0) v = fmin(v, g.r[j] * dth / xt);
+        if (xz > 0.0) v = fmin(v, dzs / xz);
+      }
+      cfl_part[set] = v;
+    }
+  }
+}
+
 // Spectral terms added to output field f at (j, m, kk): in mode (0,0) the
 // mean-flow products U x Omega and -U_r dT_m/dr (r only, formed exactly),
 // and the buoyancy Gr T in the axial component.  mean[.][j]: U_r, V, W, T_m,
@@ -423,12 +647,12 @@ __device__ void cfl_reduce(const double *__restrict__ part, int n, double *out, 
 template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz, const C2<T> *__restrict__ W,
                        const double2 *__restrict__ u, double2 *__restrict__ nh,
-                       const C2<T> *__restrict__ tw, int tm, double scale,
+                       const TwT<T> *__restrict__ tw, int tm, double scale,
                        const double *__restrict__ mean, const double *__restrict__ cfl_part,
                        int cfl_n, double *cfl_out, double *cfl_host) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nz;
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + d.nz);
   // the first workgroup dispatched also reduces the CFL bounds of the theta
   // pass (complete: that kernel ended before this one started)
   if (cfl_out && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0)
@@ -447,7 +671,20 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
     buf[li * ls + PD<T>(b)] = in[(size_t)b * d.mt + mt0 + li];
   }
   __syncthreads();
-  fft_block<T, false, kMaxB, NF>(buf, nl, ls, pz, tws);
+  if constexpr (NF > 0) {
+    // fixed lengths: radix 3 last, whose middle third of outputs (|k| > K,
+    // dropped by the truncation) is not stored
+    const int nw = (int)(blockDim.x >> 6), wv = (int)(threadIdx.x >> 6);
+    const int per = (nl + nw - 1) / nw;
+    const int l0 = wv * per;
+    const int cnt = nl - l0 < per ? nl - l0 : per;
+    if (cnt > 0)
+      fft_wave_ct_ord<T, false, NF, ORD_PLAN, 0, true>(buf + l0 * ls, cnt, tws,
+                                                       (int)(threadIdx.x & 63));
+    __syncthreads();
+  } else {
+    fft_block<T, false, kMaxB, NF>(buf, nl, ls, pz, tws);
+  }
   const size_t plane = (size_t)d.nmodes;
   for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
     const int li = w.r;
@@ -483,10 +720,10 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
 template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads)
 k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict__ W,
-           const C2<T> *__restrict__ tw, int tm, double scale) {
+           const TwT<T> *__restrict__ tw, int tm, double scale) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nz;
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + d.nz);
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
@@ -527,9 +764,9 @@ k_zinv_adj(Dims d, FftPlan pz, const double2 *__restrict__ nb, C2<T> *__restrict
 template <typename T, bool WAVE, int NF>
 __global__ void __launch_bounds__(WAVE ? kThetaWaveThreads : kFftThreads)
 k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__ W,
-            const C2<T> *__restrict__ tw, int n_in, int n_out) {
+            const TwT<T> *__restrict__ tw, int n_in, int n_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
   const int nt = d.nt, mt = d.mt;
   const int ls = lds_line<T>(nt);
   const int npi = (n_in + 1) / 2;
@@ -539,7 +776,7 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
   __syncthreads();
   if (grp.set >= d.nz * d.nr) return;
   const int j = grp.set / d.nz, b = grp.set - j * d.nz;
-  C2<T> *buf = tws + nt + (size_t)grp.slot * (npi + 2) * ls;
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + nt) + (size_t)grp.slot * (npi + 2) * ls;
   const size_t fstride = (size_t)d.nr * d.nz * mt;
   C2<T> *zl = Z + ((size_t)j * d.nz + b) * mt;
   const C2<T> *wl = W + ((size_t)j * d.nz + b) * mt;
@@ -590,10 +827,10 @@ k_theta_adj(Dims d, FftPlan pt, C2<T> *__restrict__ Z, const C2<T> *__restrict__
 template <typename T, int NF>
 __global__ void __launch_bounds__(kFftThreads)
 k_zfwd_adj(Dims d, FftPlan pz, const C2<T> *__restrict__ Z, double2 *__restrict__ db,
-           const C2<T> *__restrict__ tw, int tm) {
+           const TwT<T> *__restrict__ tw, int tm) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T> *tws = reinterpret_cast<C2<T> *>(smem);
-  C2<T> *buf = tws + d.nz;
+  TwT<T> *tws = reinterpret_cast<TwT<T> *>(smem);
+  C2<T> *buf = reinterpret_cast<C2<T> *>(tws + d.nz);
   int bx, j, f;
   xcd_block(bx, j, f);
   const int nz = d.nz, K = d.kmax, mz = d.mz;
@@ -698,7 +935,7 @@ int block_for(const FftPlan &p, int nlines, int floor_threads) {
 
 // Lines per block for the z passes: LDS budget and butterfly budget.
 int z_lines(const nsc_ctx *c, size_t esize) {
-  const size_t budget = (size_t)c->lds_max - (size_t)c->d.nz * esize;
+  const size_t budget = (size_t)c->lds_max - (size_t)c->d.nz * 16;  // twiddle entries
   int tm = (int)(budget / ((size_t)line_len(c->d.nz, esize) * esize));
   // lines beyond one butterfly per thread are transformed in groups; the
   // width of the transposed accesses (tm consecutive theta modes) matters more
@@ -734,7 +971,7 @@ struct ThetaLaunch {
 ThetaLaunch theta_launch(const nsc_ctx *c, int nlines, size_t esize, bool one_line = false) {
   ThetaLaunch L;
   const size_t line = (size_t)line_len(c->d.nt, esize) * esize;
-  const size_t tws = (size_t)c->d.nt * esize;
+  const size_t tws = (size_t)c->d.nt * 16;  // 16-byte twiddle entries in both precisions
   const int nsets = c->d.nz * c->d.nr;
   // wavefront scope: lines that fit a wavefront's registers two at a time
   // and a line set of at most 24 KB; one_line: also one line at a time and
@@ -785,33 +1022,99 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const int threads = z_threads(c->plan_z, tm);
-  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + tw_slots<T>(c->d.nz)) * sizeof(C2<T>);
   // FP32 1536-point lines: the fixed-length wavefront stages
   return with_fixed_len<sizeof(T) == 4>(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
     hipLaunchKernelGGL((k_zinv<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
                        c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
-                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(tw),
+                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const TwT<T> *>(tw),
                        tm, 1, c->s_mean);
     return hipGetLastError();
   });
 }
 
+// Launch shape of the fixed-length theta kernel: G threads per line set,
+// line pad period 2^SH, and the sets per workgroup that put the most line
+// sets on a compute unit's LDS (up to 1024 threads); sets = 0 if one set
+// does not fit.
+struct FxLaunch {
+  int sets;
+  dim3 grid;
+  size_t shm;
+};
+
+FxLaunch fx_launch(const nsc_ctx *c, size_t esize, int np, int G, int SH) {
+  const int nt = c->d.nt;
+  const size_t line = (size_t)(nt + (nt >> SH) + 1) * esize;
+  const size_t tws = (size_t)nt * 16;
+  FxLaunch L{0, dim3(1), 0};
+  int best = 0;
+  for (int s = 1; s * G <= kFftThreads; ++s) {
+    const size_t shm = tws + (size_t)s * np * line;
+    if (shm > (size_t)c->lds_max) break;
+    const int per_cu = (int)((size_t)c->lds_cu / shm) * s;
+    if (per_cu > best) {
+      best = per_cu;
+      L.sets = s;
+      L.shm = shm;
+    }
+  }
+  if (L.sets > 0) {
+    const int nsets = c->d.nz * c->d.nr;
+    L.grid = dim3((nsets + L.sets - 1) / L.sets);
+  }
+  return L;
+}
+
+template <typename T, int N, int G, int SH>
+hipError_t theta_fx(const nsc_ctx *c, const T *tw, int want_cfl, double dth, double dzs) {
+  const bool heated = c->n_in > 6;
+  const FxLaunch L = fx_launch(c, sizeof(C2<T>), heated ? 5 : 3, G, SH);
+  if (L.sets == 0) return hipErrorInvalidValue;  // (callers check theta_fits first)
+  auto kern = heated ? k_theta_fx<T, N, 9, G, SH> : k_theta_fx<T, N, 6, G, SH>;
+  hipLaunchKernelGGL(kern, L.grid, dim3(L.sets * G), L.shm, c->stream, c->d, c->g,
+                     reinterpret_cast<const C2<T> *>(c->zbuf), reinterpret_cast<C2<T> *>(c->wbuf),
+                     reinterpret_cast<const TwT<T> *>(tw), dth, dzs, c->cfl_part, want_cfl,
+                     c->s_mean);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t theta_impl(const nsc_ctx *c, const T *tw, int want_cfl) {
-  const int npi = (c->n_in + 1) / 2;
-  const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>), true);
   const double dth = 2.0 * M_PI / c->d.nt;
   const double dzs = c->d.lz / c->d.nz;
-  return with_fixed_len(c->d.nt, L.wave, [&](auto nf) {
-    constexpr int NF = decltype(nf)::value;
-    auto kern = L.wave ? k_theta<T, true, NF> : k_theta<T, false, 0>;
-    hipLaunchKernelGGL(kern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->g,
-                       c->plan_t, reinterpret_cast<const C2<T> *>(c->zbuf),
-                       reinterpret_cast<C2<T> *>(c->wbuf),
-                       reinterpret_cast<const C2<T> *>(tw), c->n_in, dth, dzs,
-                       c->cfl_part, want_cfl, c->s_mean);
-    return hipGetLastError();
-  });
+  // fixed lengths: the pruned, fused-packing kernel, one wavefront per line
+  // set for the short lines, a workgroup-scope group per set for the long
+  switch (c->d.nt) {
+    case 48: return theta_fx<T, 48, 64, 3>(c, tw, want_cfl, dth, dzs);
+    case 96: return theta_fx<T, 96, 64, 3>(c, tw, want_cfl, dth, dzs);
+    case 192: return theta_fx<T, 192, 64, 3>(c, tw, want_cfl, dth, dzs);
+    case 768: return theta_fx<T, 768, 192, 3>(c, tw, want_cfl, dth, dzs);
+    case 1536:
+      if constexpr (sizeof(T) == 4) return theta_fx<T, 1536, 512, 5>(c, tw, want_cfl, dth, dzs);
+      break;
+    default: break;
+  }
+  // other lengths: the runtime-length stages
+  const int npi = (c->n_in + 1) / 2;
+  const ThetaLaunch L = theta_launch(c, npi, sizeof(C2<T>), true);
+  auto kern = L.wave ? k_theta<T, true, 0> : k_theta<T, false, 0>;
+  hipLaunchKernelGGL(kern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->g, c->plan_t,
+                     reinterpret_cast<const C2<T> *>(c->zbuf), reinterpret_cast<C2<T> *>(c->wbuf),
+                     reinterpret_cast<const TwT<T> *>(tw), c->n_in, dth, dzs, c->cfl_part,
+                     want_cfl, c->s_mean);
+  return hipGetLastError();
+}
+
+// Launch parameters (G, SH) of the fixed-length theta kernel for the padded
+// length nt at the given precision; false where the runtime-length kernel runs.
+bool theta_fixed(int nt, bool fp32, int *G, int *SH) {
+  switch (nt) {
+    case 48: case 96: case 192: *G = 64; *SH = 3; return true;
+    case 768: *G = 192; *SH = 3; return true;
+    case 1536: *G = 512; *SH = 5; return fp32;
+    default: return false;
+  }
 }
 
 template <typename T>
@@ -820,13 +1123,13 @@ hipError_t zfwd_impl(const nsc_ctx *c, const double *u, double *nh, const T *tw,
   const int tm = z_lines(c, sizeof(C2<T>));
   dim3 grid((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
   const int threads = z_threads(c->plan_z, tm);
-  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
+  const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + tw_slots<T>(c->d.nz)) * sizeof(C2<T>);
   const double scale = 1.0 / ((double)c->d.nt * (double)c->d.nz);
   return with_fixed_len<sizeof(T) == 4>(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
     hipLaunchKernelGGL((k_zfwd<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
                        c->d, c->g, c->plan_z, reinterpret_cast<const C2<T> *>(c->wbuf),
                        reinterpret_cast<const double2 *>(u), reinterpret_cast<double2 *>(nh),
-                       reinterpret_cast<const C2<T> *>(tw), tm, scale, c->s_mean, c->cfl_part,
+                       reinterpret_cast<const TwT<T> *>(tw), tm, scale, c->s_mean, c->cfl_part,
                        c->cfl_nblk, cfl_out, cfl_host);
     return hipGetLastError();
   });
@@ -838,7 +1141,7 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
                               const T *twz, const T *twt) {
   const int tm = z_lines(c, sizeof(C2<T>));
   const int zthreads = z_threads(c->plan_z, tm);
-  const size_t zshm = ((size_t)tm * lds_line<T>(c->d.nz) + c->d.nz) * sizeof(C2<T>);
+  const size_t zshm = ((size_t)tm * lds_line<T>(c->d.nz) + tw_slots<T>(c->d.nz)) * sizeof(C2<T>);
   // forward fields on the (r, theta-spectral, z-physical) grid
   const dim3 gin((c->d.mt + tm - 1) / tm, c->d.nr, c->n_in);
   const dim3 gout((c->d.mt + tm - 1) / tm, c->d.nr, c->n_out);
@@ -847,11 +1150,11 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
     constexpr int NF = decltype(nf)::value;
     hipLaunchKernelGGL((k_zinv<T, NF>), gin, dim3(zthreads), zshm, c->stream, c->d, c->g,
                        c->plan_z, reinterpret_cast<const double2 *>(u),
-                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const C2<T> *>(twz),
+                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const TwT<T> *>(twz),
                        tm, 0, c->s_mean);
     hipLaunchKernelGGL((k_zinv_adj<T, NF>), gout, dim3(zthreads), zshm, c->stream, c->d,
                        c->plan_z, reinterpret_cast<const double2 *>(nbar),
-                       reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const C2<T> *>(twz),
+                       reinterpret_cast<C2<T> *>(c->wbuf), reinterpret_cast<const TwT<T> *>(twz),
                        tm, scale);
     return hipGetLastError();
   });
@@ -864,7 +1167,7 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
     hipLaunchKernelGGL(tkern, L.grid, dim3(L.threads), L.shm, c->stream, c->d, c->plan_t,
                        reinterpret_cast<C2<T> *>(c->zbuf),
                        reinterpret_cast<const C2<T> *>(c->wbuf),
-                       reinterpret_cast<const C2<T> *>(twt), c->n_in, c->n_out);
+                       reinterpret_cast<const TwT<T> *>(twt), c->n_in, c->n_out);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -872,7 +1175,7 @@ hipError_t nonlinear_vjp_impl(const nsc_ctx *c, const double *u, const double *n
     hipLaunchKernelGGL((k_zfwd_adj<T, decltype(nf)::value>), gin, dim3(zthreads), zshm,
                        c->stream, c->d, c->plan_z, reinterpret_cast<const C2<T> *>(c->zbuf),
                        reinterpret_cast<double2 *>(c->s_adj),
-                       reinterpret_cast<const C2<T> *>(twz), tm);
+                       reinterpret_cast<const TwT<T> *>(twz), tm);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -892,6 +1195,9 @@ hipError_t launch_zinv(const nsc_ctx *c, int prec, const double *u) {
 bool theta_fits(const nsc_ctx *c, int prec, int adjoint) {
   const int npi = (c->n_in + 1) / 2;
   const size_t esize = prec == NSC_MIXED ? sizeof(C2<float>) : sizeof(C2<double>);
+  int G, SH;
+  if (!adjoint && theta_fixed(c->d.nt, prec == NSC_MIXED, &G, &SH))
+    return fx_launch(c, esize, npi, G, SH).sets > 0;
   return theta_launch(c, adjoint ? npi + 2 : npi, esize, !adjoint).shm <= (size_t)c->lds_max;
 }
 

@@ -119,15 +119,21 @@ void cc_weights_host(int npts, double *w) {
   }
 }
 
+// e^{-2 pi i t/n}, t = 0..n-1: FP64 pairs (re, im), and for the FP32
+// transforms compensated entries (hi.re, hi.im, lo.re, lo.im), hi the FP32
+// rounding of the value and lo the FP32 rounding of what hi leaves out.
 void twiddles(int n, double *t64, float *t32) {
   const long double pi = 3.14159265358979323846264338327950288L;
   for (int t = 0; t < n; ++t) {
     const long double a = 2.0L * pi * (long double)t / (long double)n;
-    const double c = (double)cosl(a), s = -(double)sinl(a);
-    t64[2 * t] = c;
-    t64[2 * t + 1] = s;
-    t32[2 * t] = (float)cosl(a);
-    t32[2 * t + 1] = -(float)sinl(a);
+    const long double c = cosl(a), s = -sinl(a);
+    t64[2 * t] = (double)c;
+    t64[2 * t + 1] = (double)s;
+    const float hc = (float)c, hs = (float)s;
+    t32[4 * t] = hc;
+    t32[4 * t + 1] = hs;
+    t32[4 * t + 2] = (float)(c - (long double)hc);
+    t32[4 * t + 3] = (float)(s - (long double)hs);
   }
 }
 
@@ -235,6 +241,30 @@ int solve_impl(nsc_ctx *c, const double *un, const double *nn, const double *nq,
     HIPCHK(launch_finalize(c, out, pout));
   }
   return NSC_OK;
+}
+
+// Non-finite check of a fixed-size step: its first nonlinear stage writes the
+// CFL bound of the step's input state (NaN if a value was not finite) to the
+// host-mapped scalar and records ev_cfl.  At the end of the call the host
+// reads it if the stage has finished, without waiting; otherwise the check
+// stays pending and the next step call waits for it (by then long done).
+int query_nonfinite(nsc_ctx *c) {
+  const hipError_t q = hipEventQuery(c->ev_cfl);
+  if (q == hipErrorNotReady) {
+    (void)hipGetLastError();  // not an error: leave nothing for the next launch check
+    c->nan_pending = 1;
+    return NSC_OK;
+  }
+  if (q != hipSuccess) return NSC_ERR_DEVICE;
+  c->nan_pending = 0;
+  return std::isnan(c->h_pinned[0]) ? NSC_ERR_NONFINITE : NSC_OK;
+}
+
+int pending_nonfinite(nsc_ctx *c) {
+  if (!c->nan_pending) return NSC_OK;
+  c->nan_pending = 0;
+  HIPCHK(hipEventSynchronize(c->ev_cfl));
+  return std::isnan(c->h_pinned[0]) ? NSC_ERR_NONFINITE : NSC_OK;
 }
 
 }  // namespace
@@ -430,14 +460,14 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   // twiddles
   {
     std::vector<double> t64(2 * d.nt);
-    std::vector<float> t32(2 * d.nt);
+    std::vector<float> t32(4 * d.nt);
     twiddles(d.nt, t64.data(), t32.data());
     TRY(dmalloc((void **)&c->tw64_t, t64.size() * sizeof(double)));
     TRY(dmalloc((void **)&c->tw32_t, t32.size() * sizeof(float)));
     HIPCHK(hipMemcpy(c->tw64_t, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->tw32_t, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
     std::vector<double> z64(2 * d.nz);
-    std::vector<float> z32(2 * d.nz);
+    std::vector<float> z32(4 * d.nz);
     twiddles(d.nz, z64.data(), z32.data());
     TRY(dmalloc((void **)&c->tw64_z, z64.size() * sizeof(double)));
     TRY(dmalloc((void **)&c->tw32_z, z32.size() * sizeof(float)));
@@ -556,9 +586,11 @@ int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
   const double dt = *dt_inout;
   if (!(dt > 0.0 && std::isfinite(dt))) return NSC_ERR_ARG;
   const bool dyn = c->dynamic != 0;
-  // the bound lands in the host-mapped pinned scalar; the event marks it
-  TRY(nonlinear_impl(c, u, c->s_nn, dyn ? c->cfl_val : nullptr, c->h_pinned_dev));
-  if (dyn) HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
+  TRY(pending_nonfinite(c));
+  // the bound (NaN for a non-finite state) lands in the host-mapped pinned
+  // scalar; the event marks it
+  TRY(nonlinear_impl(c, u, c->s_nn, c->cfl_val, c->h_pinned_dev));
+  HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
   // predictor, then correctors; the last stage writes u in place (the
   // finalising kernel reads only library scratch, never u^n)
   TRY(solve_impl(c, u, c->s_nn, c->s_nn, c->n_corr == 0 ? u : c->s_u1, nullptr, dt, c->c, 1));
@@ -566,19 +598,18 @@ int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
     TRY(nonlinear_impl(c, c->s_u1, c->s_nq, nullptr));
     TRY(solve_impl(c, u, c->s_nn, c->s_nq, q == c->n_corr ? u : c->s_u1, nullptr, dt, c->c, 1));
   }
-  if (dyn) {
-    HIPCHK(hipEventSynchronize(c->ev_cfl));
-    const double dtc = c->h_pinned[0];
-    if (std::isnan(dtc)) return NSC_ERR_NONFINITE;
-    // hysteresis: shrink to 0.9 of the bound when exceeded, grow (to 0.9 of
-    // the bound, capped by dt_max) only past +20 %
-    const double b = c->cfl * dtc;
-    double next = dt;
-    if (b < dt) next = 0.9 * b;
-    else if ((b < c->dt_max ? b : c->dt_max) > 1.2 * dt) next = (0.9 * b < c->dt_max ? 0.9 * b : c->dt_max);
-    if (!(next >= 1e-12)) return NSC_ERR_DT;
-    *dt_inout = next;
-  }
+  if (!dyn) return query_nonfinite(c);
+  HIPCHK(hipEventSynchronize(c->ev_cfl));
+  const double dtc = c->h_pinned[0];
+  if (std::isnan(dtc)) return NSC_ERR_NONFINITE;
+  // hysteresis: shrink to 0.9 of the bound when exceeded, grow (to 0.9 of
+  // the bound, capped by dt_max) only past +20 %
+  const double b = c->cfl * dtc;
+  double next = dt;
+  if (b < dt) next = 0.9 * b;
+  else if ((b < c->dt_max ? b : c->dt_max) > 1.2 * dt) next = (0.9 * b < c->dt_max ? 0.9 * b : c->dt_max);
+  if (!(next >= 1e-12)) return NSC_ERR_DT;
+  *dt_inout = next;
   return NSC_OK;
 }
 
@@ -625,15 +656,18 @@ int nsc_step_stages(nsc_ctx *c, const double *u, double *stages, double *u_next)
   if (nc > 0 && (u_next < stages + nc * fld && stages < u_next + fld)) return NSC_ERR_ARG;
   if (nc > 0 && (u < stages + nc * fld && stages < u + fld)) return NSC_ERR_ARG;
   double *xs = const_cast<double *>(u);
-  // same sequence as nsc_step: N(u); X^(1) = S(u, N, N); X^(q+1) = S(u, N, N(X^(q)))
-  TRY(nonlinear_impl(c, xs, c->s_nn, nullptr));
+  TRY(pending_nonfinite(c));
+  // same sequence as nsc_step: N(u); X^(1) = S(u, N, N); X^(q+1) = S(u, N, N(X^(q)));
+  // the first nonlinear stage's bound serves the non-finite check
+  TRY(nonlinear_impl(c, xs, c->s_nn, c->cfl_val, c->h_pinned_dev));
+  HIPCHK(hipEventRecord(c->ev_cfl, c->stream));
   TRY(solve_impl(c, xs, c->s_nn, c->s_nn, nc == 0 ? u_next : stages, nullptr, c->dt, c->c, 1));
   for (int q = 1; q <= nc; ++q) {
     TRY(nonlinear_impl(c, stages + (size_t)(q - 1) * fld, c->s_nq, nullptr));
     TRY(solve_impl(c, xs, c->s_nn, c->s_nq, q == nc ? u_next : stages + (size_t)q * fld, nullptr,
                    c->dt, c->c, 1));
   }
-  return NSC_OK;
+  return query_nonfinite(c);
 }
 
 int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double *ubar_next,

@@ -89,7 +89,7 @@ struct nsc_ctx {
   nsc::Grid g{};
   void *tables = nullptr;  // single allocation backing g
   double *tw64_t = nullptr, *tw64_z = nullptr;  // [n][2] twiddles e^{-2 pi i t/n}
-  float *tw32_t = nullptr, *tw32_z = nullptr;
+  float *tw32_t = nullptr, *tw32_z = nullptr;   // [n][4] compensated (hi, lo) twiddles
   nsc::FftPlan plan_t{}, plan_z{};
   // factors
   nsc::Factors fv{}, ft{}, fp{};
@@ -117,6 +117,7 @@ struct nsc_ctx {
   double *h_pinned = nullptr;  // pinned host scalar(s)
   double *h_pinned_dev = nullptr;  // its device-side address (kernels write the CFL bound)
   hipEvent_t ev_cfl = nullptr;
+  int nan_pending = 0;  // a fixed-size step's non-finite check not read yet
   // profiling
   int profiling = 0;
   double stage_ms[nsc::kNumStages] = {0};
