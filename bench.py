@@ -2,14 +2,19 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Workload (default tc-heated-n64): heated Taylor--Couette, eta = 0.71,
+Main line (value): the heated workload tc-heated-n64 -- eta = 0.71,
 Re_i = 100, Re_o = 0, Ra = 1e4, Pr = 0.7, N_r = 64, 64 x 127 Fourier modes
 (192 x 192 padded grid), seeded synthetic initial state, dynamic time step
-(CFL 0.5).  One step = nonlinear term + predictor solve + nonlinear term +
-corrector solve.  Prints one JSON line: mixed-precision steps/s (value), the
-FP64 steps/s on the same grid, the mixed-vs-FP64 error per field, the
-roofline figures of the dominant kernel (HIP events on the library stream)
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+(CFL 0.5) -- in mixed precision (FP32 transforms and products, FP64
+solves).  One step = nonlinear term + predictor solve + nonlinear term +
+corrector solve.  The JSON line also carries the FP64 steps/s on the same
+grid, the mixed-vs-FP64 error per field (relative to the field and to its
+deviation from the basic state), the roofline of the dominant kernel (HIP
+events on the library stream), every other workload's steps/s and kernel
+rooflines (per_config: mixed and FP64, FP64 left out where its theta line
+set does not fit the LDS), the adjoint/forward cost ratio on the adjoint
+workload's schedule (200 steps, checkpoint every 20) and the FP64 CPU oracle
+timed on a bounded sample of the main workload.
 """
 import argparse
 import json
@@ -75,11 +80,9 @@ def kernel_bytes(name, w, prec):
     return 0
 
 
-# device kernel behind each timed stage of the default workload (mixed
-# precision, the reported value; 192-point transforms)
-DEVICE_KERNEL_WORKLOAD = "tc-heated-n64"
-DEVICE_KERNEL = {"zinv": "nsc::k_zinv<float, 192>", "theta": "nsc::k_theta<float, true, 192>",
-                 "zfwd": "nsc::k_zfwd<float, 192>", "rhs": "nsc::k_rhs<4>", "div": "nsc::k_div2<2>",
+# device kernel behind each timed solve stage of the default workload (the
+# transform kernels depend on the grid: _kernel_name)
+DEVICE_KERNEL = {"rhs": "nsc::k_rhs<4>", "div": "nsc::k_div2<2>",
                  "sweep_pt": "nsc::k_sweep<true, 0, 64>", "sweep_vel": "nsc::k_sweep<true, 1, 64>",
                  "vel_rhs": "nsc::k_vel_rhs<1>", "finalize": "nsc::k_finalize<false>",
                  "influence": "nsc::k_influence"}
@@ -98,13 +101,14 @@ def source_digest():
     return h.hexdigest()
 
 
-def committed_traffic(wname, stage):
+def committed_traffic(wname, stage, w):
     """HBM bytes per launch of a stage's kernel from the committed counter
     summary profiles/hbm-traffic_<workload>.txt (FETCH_SIZE + WRITE_SIZE,
     each scaled by the calibration kernel's reading), or None when the file
     is missing or the kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"hbm-traffic_{wname}.txt")
-    if wname != DEVICE_KERNEL_WORKLOAD or not os.path.exists(path) or stage not in DEVICE_KERNEL:
+    name = _kernel_name(stage, w)
+    if name is None or not os.path.exists(path):
         return None
     digest, rows = None, {}
     with open(path) as fh:
@@ -116,7 +120,7 @@ def committed_traffic(wname, stage):
                 rows[" ".join(parts[2:])] = float(parts[1])
     if digest != source_digest():
         return None
-    return rows.get(DEVICE_KERNEL[stage])
+    return rows.get(name)
 
 
 def calibration_copy():
@@ -134,10 +138,32 @@ def calibration_copy():
     del src, dst, evict
 
 
-def run_gpu(args, wname):
+def _kernel_name(stage, w):
+    """Device kernel behind a timed stage in mixed precision on workload w
+    (the transform kernels are compiled for the padded lengths of the
+    configured grids; the theta pass of 1536-point lines runs the
+    runtime-length, workgroup-scope kernel)."""
+    nt = 3 * w["M_theta"]
+    nz = 3 * ((w["M_z"] - 1) // 2 + 1)
+    if stage == "theta":
+        return (f"nsc::k_theta<float, true, {nt}>" if nt in (48, 96, 192, 768)
+                else "nsc::k_theta<float, false, 0>")
+    if stage in ("zinv", "zfwd"):
+        ln = nz if nz in (48, 96, 192, 768, 1536) else 0
+        return f"nsc::k_{stage}<float, {ln}>"
+    return DEVICE_KERNEL.get(stage)
+
+
+def measure(wname, steps, warmup, precisions=("fp64", "mixed"), profile_steps=50):
+    """Steps/s of one workload per precision (HIP-synchronised wall time of
+    `steps` steps after `warmup` untimed ones), the mixed-vs-FP64 error per
+    field, and each kernel's device time from the library's stage timer
+    (HIP events on its stream) over a separate run of min(steps,
+    profile_steps) mixed steps."""
     import torch
 
     import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd._lib import NSC_ERR_STATE, NscError
     from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
 
     w = WORKLOADS[wname]
@@ -145,26 +171,28 @@ def run_gpu(args, wname):
     ctx = nsc.Context(*params(wname))
     amps = amplitudes(wname).cuda()
     u0 = ctx.initial_state(amps)
+    base = ctx.initial_state(0 * amps)  # the basic state: Couette flow (and conduction)
     dt_max = w["dt"]
     if w["dynamic"]:
+        ctx.set_precision("mixed")
         _, c = ctx.nonlinear(u0, cfl=True)
         dt0 = min(dt_max, 0.5 * float(c.cpu()[0]))
     else:
         dt0 = w["dt"]
 
-    def run(prec, steps, warmup, profile=False):
+    def run(prec, nsteps, nwarm, profile=False, dynamic=w["dynamic"]):
         ctx.set_precision(prec)
-        ctx.set_timestep(dt=dt0, dynamic=w["dynamic"], cfl=0.5, dt_max=dt_max)
+        ctx.set_timestep(dt=dt0, dynamic=dynamic, cfl=0.5, dt_max=dt_max)
         u = u0.clone()
         dt = dt0
-        for _ in range(warmup):
+        for _ in range(nwarm):
             dt = ctx.step(u, dt)
         torch.cuda.synchronize()
         if profile:
             ctx.timings()
             ctx.set_profiling(True)
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(nsteps):
             dt = ctx.step(u, dt)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
@@ -172,53 +200,81 @@ def run_gpu(args, wname):
         if profile:
             ctx.set_profiling(False)
             tim = ctx.timings()
-        return el, u, dt, tim
+        return el, u, tim
 
-    K, W = args.steps, args.warmup
-    # untimed warm-up run of both precisions (first factorisation, code load)
-    run("fp64", 2, 0)
-    run("mixed", 2, 0)
-    t64, u64, dt64, _ = run("fp64", K, W)
-    tmx, umx, dtmx, _ = run("mixed", K, W)
-    # per-kernel durations: same K steps again, each kernel between HIP events
-    _, _, _, tim = run("mixed", min(K, 50), W, profile=True)
-
-    def wnorm(x):
-        return float(torch.linalg.vector_norm(x))
-
-    err = {}
-    names = ["u_r", "u_theta", "u_z", "T"][:ctx.F]
-    for f, nm in enumerate(names):
-        err[nm] = wnorm(umx[f] - u64[f]) / max(wnorm(u64[f]), 1e-300)
-
-    # dominant kernel and its roofline
-    best = None
-    for kname, (ms, cnt) in tim.items():
-        if cnt == 0 or kname in ("factor", "remap"):
+    res = {"workload": wname, "steps": steps, "warmup": warmup}
+    out = {}
+    skipped = {}
+    for prec in precisions:
+        try:
+            run(prec, 2, 0)  # untimed: first factorisation, code load
+        except NscError as e:
+            if e.code != NSC_ERR_STATE:
+                raise
+            skipped[prec] = ("the FP64 theta line set (all fields of one padded line "
+                             "with the twiddles) exceeds one workgroup's LDS on this grid")
             continue
-        if best is None or ms > best[1]:
-            best = (kname, ms, cnt)
-    kname, ms, cnt = best
-    avg_s = ms / cnt / 1e3
-    byt = kernel_bytes(kname, w, "mixed")
-    achieved = byt / avg_s / 1e9
-    per_kernel = {k: {"ms_total": round(v[0], 4), "launches": v[1],
-                      "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else None,
-                      "GBps": round(kernel_bytes(k, w, "mixed") / (v[0] / v[1] / 1e3) / 1e9, 1)
-                      if v[1] and kernel_bytes(k, w, "mixed") else None}
-                  for k, v in tim.items()}
+        el, _, _ = run(prec, steps, warmup)
+        out[prec] = el
+        res[prec] = {"steps_per_s": round(steps / el, 3), "ms_per_step": round(1e3 * el / steps, 4)}
+    for prec, why in skipped.items():
+        res[prec] = {"skipped": why}
+    if "fp64" in out and "mixed" in out:
+        # error of the mixed path: both precisions over the same fixed steps
+        # (the dynamic control could pick different step sizes), from u0
+        ncmp = min(steps, 20)
+        res["error_steps"] = f"{ncmp} steps at the fixed dt {dt0:.4g} from the initial state"
+        umx = run("mixed", ncmp, 0, dynamic=False)[1]
+        u64 = run("fp64", ncmp, 0, dynamic=False)[1]
+        names = ["u_r", "u_theta", "u_z", "T"][:ctx.F]
+        nrm = lambda x: float(torch.linalg.vector_norm(x))  # noqa: E731
+        res["mixed_vs_fp64_rel_err"] = {
+            nm: float(f"{nrm(umx[f] - u64[f]) / max(nrm(u64[f]), 1e-300):.3e}")
+            for f, nm in enumerate(names)}
+        # relative to the field's deviation from the basic state (u_r has none)
+        res["mixed_vs_fp64_pert_rel_err"] = {
+            nm: float(f"{nrm(umx[f] - u64[f]) / max(nrm(u64[f] - base[f]), 1e-300):.3e}")
+            for f, nm in enumerate(names)}
+        res["mixed_speedup_vs_fp64"] = round(out["fp64"] / out["mixed"], 3)
+        del umx, u64
+    del out
+    if "mixed" in precisions:
+        _, _, tim = run("mixed", min(steps, profile_steps), warmup, profile=True)
+        kern = {}
+        for k, (ms, cnt) in tim.items():
+            if cnt == 0 or k in ("remap",):
+                continue
+            byt = kernel_bytes(k, w, "mixed")
+            avg_s = ms / cnt / 1e3
+            e = {"avg_us": round(1e6 * avg_s, 3), "launches": cnt}
+            if byt:
+                gbs = byt / avg_s / 1e9
+                e.update(bytes_per_launch=byt, GBps=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
+            kern[k] = e
+        best = max((k for k in kern if k not in ("factor",)),
+                   key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+        kb = kern[best]
+        res["roofline"] = {"bound": "hbm", "kernel": best, "device_kernel": _kernel_name(best, w),
+                           "achieved": kb["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": kb["frac"],
+                           "traffic": committed_traffic(wname, best, w),
+                           "bytes_per_launch": kb["bytes_per_launch"],
+                           "avg_launch_us": kb["avg_us"]}
+        res["kernels"] = kern
     ctx.close()
-    calibration_copy()
-    return dict(K=K, W=W, t64=t64, tmx=tmx, err=err, dt_end=(dt64, dtmx), dominant=kname,
-                avg_us=avg_s * 1e6, bytes=byt, achieved=achieved, per_kernel=per_kernel)
+    del u0, base, amps, ctx
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
 
 
-def run_adjoint(steps, wname="tc-adjoint-n64", ckpt=20):
-    """Adjoint/forward cost ratio on the adjoint workload (eta = 0.71,
-    Re_i = 200, N_r = 64, 32 x 63 modes, dt = 5e-4): wall time of the
-    gradient pass (checkpoint recompute + vector-Jacobian products) over the
-    wall time of the plain forward rollout of the same steps, both after an
-    untimed warm-up of each."""
+def run_adjoint(steps=200, wname="tc-adjoint-n64", ckpt=20):
+    """Adjoint/forward cost ratio on the adjoint workload's schedule (eta =
+    0.71, Re_i = 200, N_r = 64, 32 x 63 modes, dt = 5e-4, 200 steps,
+    checkpoint every 20): wall time of the gradient pass (checkpoint
+    recompute + vector--Jacobian products) over the wall time of the plain
+    forward rollout of the same steps, both after an untimed warm-up of
+    each."""
     import torch
 
     import paper_1908_00587_amd as nsc
@@ -251,6 +307,64 @@ def run_adjoint(steps, wname="tc-adjoint-n64", ckpt=20):
             "ratio": round(t_bwd / t_fwd, 3)}
 
 
+def run_adjoint_largest():
+    """The largest workload's adjoint schedule (N_r = 256, 512 x 1023 modes,
+    mixed precision): 100 steps at a fixed CFL-sized dt = 2e-6, then the
+    gradient of the final perturbation energy over the last 50 with a
+    checkpoint every 10, checkpoints in pinned host memory and stage states
+    recomputed per step (the backward pass's memory options, which this
+    grid needs on one GPU).  Ratio = (energy + gradient pass) / forward
+    rollout of the same 50 steps."""
+    import torch
+
+    import paper_1908_00587_amd as nsc
+    from paper_1908_00587_amd.adjoint import rollout, rollout_energy
+    from paper_1908_00587_amd.workloads import amplitudes, params
+
+    wname = "tc-conv-n256"
+    ctx = nsc.Context(*params(wname))
+    ctx.set_precision("mixed")
+    u = ctx.initial_state(amplitudes(wname).cuda())
+    dt = 2e-6
+    ctx.set_timestep(dt=dt)
+    for _ in range(50):
+        ctx.step(u, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u50 = u.clone()
+    u = rollout(ctx, u50, 50, dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del u
+    y = u50.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    e = rollout_energy(ctx, y, 50, dt, ckpt_every=10, offload=True, keep_stages=False)
+    e.backward()
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    free, total = torch.cuda.mem_get_info()
+    ctx.close()
+    return {"workload": wname, "steps": 50, "checkpoint_every": 10, "precision": "mixed",
+            "dt": dt, "options": "offload=True, keep_stages=False",
+            "forward_ms": round(1e3 * t_fwd, 1), "gradient_ms": round(1e3 * t_all, 1),
+            "ratio": round(t_all / t_fwd, 3),
+            "device_GiB_in_use_at_end": round((total - free) / 2**30, 1)}
+
+
+def host_cpu():
+    """Model name of the host CPU and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
 def run_cpu(wname, steps):
     import torch
 
@@ -264,9 +378,11 @@ def run_cpu(wname, steps):
     t0 = time.perf_counter()
     O.run(p, u, steps, dt0=dt0, dynamic=w["dynamic"], cfl=0.5, dt_max=w["dt"])
     el = time.perf_counter() - t0
+    model, ncpu = host_cpu()
     return dict(value=steps / el, unit="steps/s", cores=torch.get_num_threads(), kind="oracle",
                 sample=f"{steps} FP64 oracle steps of {wname} (dense LU, DFT matrices), "
-                       f"{el:.1f} s")
+                       f"{el:.1f} s",
+                cpu_model=model, affinity_cpus=ncpu)
 
 
 RESTART_FROM = "tc-heated-n64"
@@ -436,6 +552,11 @@ def pmc_summary(paths):
         print(k[:48].ljust(48) + "".join(x.rjust(wd) for x, wd in zip(cells, width)))
 
 
+# the other workloads of the per_config block: timed steps, warm-up steps
+PER_CONFIG = {"tc-iso-n32": (100, 5), "tc-heated-n64": (200, 5), "tc-adjoint-n64": (200, 5),
+              "tc-turb-n128": (20, 3), "tc-conv-n256": (5, 2)}
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2:])
@@ -453,7 +574,13 @@ def main():
     ap.add_argument("--workload", default="tc-heated-n64")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--adjoint-steps", type=int, default=40)
+    ap.add_argument("--no-per-config", action="store_true",
+                    help="time the main workload only")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--adjoint-ckpt", type=int, default=20)
+    ap.add_argument("--adjoint-largest", action="store_true",
+                    help="print the adjoint/forward ratio on the largest workload's schedule "
+                         "(about two minutes) instead of the time step")
     ap.add_argument("--restart", action="store_true",
                     help="measure the restart remap instead of the time step")
     args = ap.parse_args()
@@ -464,22 +591,34 @@ def main():
     if args.restart:
         print(json.dumps(run_restart(cpu=not args.no_cpu)), flush=True)
         return
+    if args.adjoint_largest:
+        print(json.dumps(run_adjoint_largest()), flush=True)
+        return
     from paper_1908_00587_amd.workloads import WORKLOADS
     w = WORKLOADS[args.workload]
-    g = run_gpu(args, args.workload)
-    adj = run_adjoint(args.adjoint_steps) if args.adjoint_steps > 0 else None
+    K, W = args.steps, args.warmup
+    g = measure(args.workload, K, W)
+    calibration_copy()  # the known-size kernel that scales counter readings in profiled runs
+    per = {}
+    if not args.no_per_config:
+        for wname, (k, wu) in PER_CONFIG.items():
+            if wname == args.workload:
+                continue
+            print(f"bench: per-config {wname}", file=sys.stderr, flush=True)
+            per[wname] = measure(wname, k, wu)
+    adj = (run_adjoint(args.adjoint_steps, ckpt=args.adjoint_ckpt)
+           if args.adjoint_steps > 0 else None)
     cpu = None if args.no_cpu else run_cpu(args.workload, args.cpu_steps)
-    K = g["K"]
-    mx_sps = K / g["tmx"]
-    fp_sps = K / g["t64"]
+    mx = g["mixed"]
+    fp = g.get("fp64", {})
     out = {
         "metric": METRIC,
-        "value": round(mx_sps, 2),
+        "value": mx["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": g["W"],
-        "ms_per_step": round(1e3 * g["tmx"] / K, 4),
+        "warmup": W,
+        "ms_per_step": mx["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -490,17 +629,16 @@ def main():
                    "N_z": 3 * ((w["M_z"] - 1) // 2 + 1), "Re_i": w["Re_i"], "Ra": w["Ra"],
                    "dynamic_dt": w["dynamic"], "n_corr": 1, "precision": "mixed",
                    "parallelism": "single-gpu"},
-        "fp64": {"value": round(fp_sps, 2), "unit": "steps/s",
-                 "ms_per_step": round(1e3 * g["t64"] / K, 4)},
-        "mixed_speedup_vs_fp64": round(mx_sps / fp_sps, 3),
-        "mixed_vs_fp64_rel_err": {k: float(f"{v:.3e}") for k, v in g["err"].items()},
-        "roofline": {"bound": "hbm", "kernel": g["dominant"],
-                     "achieved": round(g["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": committed_traffic(args.workload, g["dominant"]),
-                     "bytes_per_launch": g["bytes"], "avg_launch_us": round(g["avg_us"], 3)},
+        "fp64": {"value": fp.get("steps_per_s"), "unit": "steps/s",
+                 "ms_per_step": fp.get("ms_per_step")},
+        "mixed_speedup_vs_fp64": g.get("mixed_speedup_vs_fp64"),
+        "mixed_vs_fp64_rel_err": g.get("mixed_vs_fp64_rel_err"),
+        "mixed_vs_fp64_pert_rel_err": g.get("mixed_vs_fp64_pert_rel_err"),
+        "error_steps": g.get("error_steps"),
+        "roofline": g["roofline"],
+        "kernels": g["kernels"],
+        "per_config": per,
         "adjoint_forward_cost_ratio": adj,
-        "kernels": g["per_kernel"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
