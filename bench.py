@@ -164,11 +164,12 @@ def measure(wname, steps, warmup, precisions=("fp64", "mixed"), profile_steps=50
 
     import paper_1908_00587_amd as nsc
     from paper_1908_00587_amd._lib import NSC_ERR_STATE, NscError
-    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+    from paper_1908_00587_amd.workloads import (WORKLOADS, amplitudes, is_pipe, params,
+                                                pipe_params)
 
     w = WORKLOADS[wname]
     torch.cuda.set_device(0)
-    ctx = nsc.Context(*params(wname))
+    ctx = nsc.Context.pipe(*pipe_params(wname)) if is_pipe(wname) else nsc.Context(*params(wname))
     amps = amplitudes(wname).cuda()
     u0 = ctx.initial_state(amps)
     base = ctx.initial_state(0 * amps)  # the basic state: Couette flow (and conduction)
@@ -554,7 +555,7 @@ def pmc_summary(paths):
 
 # the other workloads of the per_config block: timed steps, warm-up steps
 PER_CONFIG = {"tc-iso-n32": (100, 5), "tc-heated-n64": (200, 5), "tc-adjoint-n64": (200, 5),
-              "tc-turb-n128": (20, 3), "tc-conv-n256": (5, 2)}
+              "tc-turb-n128": (20, 3), "tc-conv-n256": (5, 2), "pipe-n64": (100, 5)}
 
 
 def main():
@@ -624,11 +625,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "N_r": w["N_r"], "M_theta": w["M_theta"],
+        "config": {"workload": args.workload, "geometry": w.get("geometry", "cylinders"),
+                   "N_r": w["N_r"], "M_theta": w["M_theta"],
                    "M_z": w["M_z"], "N_theta": 3 * w["M_theta"],
-                   "N_z": 3 * ((w["M_z"] - 1) // 2 + 1), "Re_i": w["Re_i"], "Ra": w["Ra"],
-                   "dynamic_dt": w["dynamic"], "n_corr": 1, "precision": "mixed",
-                   "parallelism": "single-gpu"},
+                   "N_z": 3 * ((w["M_z"] - 1) // 2 + 1), "Re": w.get("Re", w.get("Re_i")),
+                   "Ra": w["Ra"], "dynamic_dt": w["dynamic"], "n_corr": 1,
+                   "precision": "mixed", "parallelism": "single-gpu"},
         "fp64": {"value": fp.get("steps_per_s"), "unit": "steps/s",
                  "ms_per_step": fp.get("ms_per_step")},
         "mixed_speedup_vs_fp64": g.get("mixed_speedup_vs_fp64"),

@@ -83,6 +83,30 @@ enum { NSC_FP64 = 0, NSC_MIXED = 1 };
 int nsc_init(double eta, double Re_i, double Re_o, double Ra, double Pr,
              int N_r, int M_theta, int M_z, double L_z, nsc_ctx **out);
 
+/* Create a context for the pipe-flow variant (abstract and section 4: the
+ * method, applied to flows in straight pipes).  Conventions (the paper does
+ * not print the pipe formulation; these are this library's): a pipe of
+ * radius 1, periodic in z with period L_z, time in R^2/nu, velocity in nu/R;
+ * du/dt = -grad P + lap u + u x omega + 4 Re e_z, div u = 0, u = 0 at r = 1:
+ * the flow is driven by the constant mean pressure gradient 4 Re, whose
+ * laminar solution is u_z = Re (1 - r^2).  Isothermal, F = 3.  Radial points
+ * r_j = cos(pi (N_r - 1 - j) / (2 N_r - 1)), j = 0..N_r-1 (the positive half
+ * of the 2 N_r Gauss--Lobatto points of [-1, 1]: r = 1 included, the axis
+ * not a point).  At the axis an order-m coefficient is even or odd in r as
+ * (-1)^m (u_z, pressure) or (-1)^(m+1) (u_r, u_theta): the nine-point rows
+ * reach across the axis onto the mirror points -r_k, whose weights are
+ * folded onto r_k with that sign.  One wall: the pressure correction has one
+ * influence condition, div u = 0 at r = 1.  Mode (0,0): u_r = 0; pressure
+ * head p(1) = 0.  nsc_nonlinear, nsc_radial_solve, nsc_step,
+ * nsc_set_timestep/precision/stream, nsc_initial_state (perturbation
+ * (a_r +- i a_theta) g_{m+-1}(r) for u_r +- i u_theta and a_z g_m(r) for
+ * u_z, g_q = r^q (1 - r^2)^2 at peak one, projected as for the cylinders,
+ * on Hagen--Poiseuille flow), nsc_get_grid, nsc_probe and the timing calls
+ * apply; the energy, adjoint, diagnostics and state-file calls return
+ * NSC_ERR_STATE.  Re finite; N_r, M_theta, M_z, L_z as for nsc_init.
+ * Errors: NSC_ERR_ARG, NSC_ERR_DEVICE, NSC_ERR_OOM. */
+int nsc_init_pipe(double Re, int N_r, int M_theta, int M_z, double L_z, nsc_ctx **out);
+
 /* Release the context and every device buffer it owns.  NULL is a no-op. */
 int nsc_destroy(nsc_ctx *ctx);
 

@@ -34,6 +34,7 @@ def _bind(L):
     I = ctypes.c_int
     sig = {
         "nsc_init": ([D, D, D, D, D, I, I, I, D, ctypes.POINTER(P)], I),
+        "nsc_init_pipe": ([D, I, I, I, D, ctypes.POINTER(P)], I),
         "nsc_destroy": ([P], I),
         "nsc_set_stream": ([P, P], I),
         "nsc_set_precision": ([P, I], I),

@@ -55,6 +55,29 @@ class Context:
         self._dt = 1e-3
         self._settings = dict(dt=1e-3, dynamic=0, cfl=0.5, dt_max=1e-3, n_corr=1, c=0.5)
 
+    @classmethod
+    def pipe(cls, Re, N_r, M_theta, M_z, L_z, device=None):
+        """Pipe-flow context (nsc_init_pipe): radius 1, driven by the mean
+        pressure gradient 4 Re (laminar flow Re (1 - r^2)), N_r radial points
+        between the axis and the wall, M_theta x M_z Fourier modes, period L_z."""
+        self = cls.__new__(cls)
+        self._L = _lib.lib()
+        if device is not None:
+            torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        check(self._L.nsc_init_pipe(float(Re), int(N_r), int(M_theta), int(M_z), float(L_z),
+                                    ctypes.byref(h)), "nsc_init_pipe")
+        self._h = h
+        self.eta, self.Re_i, self.Re_o, self.Ra, self.Pr = None, Re, 0.0, 0.0, 1.0
+        self.Re = Re
+        self.N_r, self.M_theta, self.M_z, self.L_z = N_r, M_theta, M_z, L_z
+        self.F = 3
+        self.shape = (3, N_r, M_theta, M_z)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._dt = 1e-3
+        self._settings = dict(dt=1e-3, dynamic=0, cfl=0.5, dt_max=1e-3, n_corr=1, c=0.5)
+        return self
+
     # -- plumbing ---------------------------------------------------------------
     def _sync_stream(self):
         s = torch.cuda.current_stream(self.device).cuda_stream

@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(kProbeThreads) k_probe(Dims d, const double2 *
 
 int nsc_diagnostics(nsc_ctx *c, const double *u_hat, double *out) {
   if (!c || !u_hat || !out) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   hipLaunchKernelGGL(nsc::k_diag, dim3(1), dim3(64), 0, c->stream, c->d, c->g,
                      reinterpret_cast<const double2 *>(u_hat), std::log(c->eta), out);
   return hipGetLastError() == hipSuccess ? NSC_OK : NSC_ERR_DEVICE;

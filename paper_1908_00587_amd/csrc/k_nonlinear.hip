@@ -49,7 +49,10 @@ struct Walk2 {
 // Field `f` of the derived set at (row j, mode m, kk): 0..2 u_r, u_theta,
 // u_z; 3..5 omega_r, omega_theta, omega_z; 6..8 grad T.  With drop_mean the
 // mode (0,0) -- the r-only mean flow, whose products are formed exactly per
-// mode in k_zfwd -- is left out of the transforms.
+// mode in k_zfwd -- is left out of the transforms.  PIPE: the radial
+// derivative of an order-m coefficient uses the rows of its parity in r,
+// (-1)^(m+1) for u_r and u_theta, (-1)^m for u_z.
+template <bool PIPE>
 __device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
                                            const double2 *__restrict__ u, int f,
                                            int j, int m, int kk, bool drop_mean) {
@@ -62,6 +65,7 @@ __device__ __forceinline__ double2 derived(const Dims &d, const Grid &g,
   auto D1 = [&](int fld) -> double2 {
     const int s = g.s[j];
     const double *w = g.d1 + j * kStencil;
+    if constexpr (PIPE) w += odd_off(g, fld == 1 ? m + 1 : m);
     double2 acc = {0.0, 0.0};
 #pragma unroll
     for (int t = 0; t < kStencil; ++t) {
@@ -113,9 +117,10 @@ __device__ void mean_row(const Dims &d, const Grid &g, const double2 *__restrict
   auto M = [&](int f, int row) { return u[((size_t)f * n + row) * P + d.kmax].x; };
   const int s = g.s[j];
   const double *w = g.d1 + j * kStencil;
+  const double *wv = w + g.podd;  // V = u_theta of order 0: odd in r in the pipe
   double dv = 0.0, dw = 0.0, dt = 0.0;
   for (int t = 0; t < kStencil; ++t) {
-    dv = fma(w[t], M(1, s + t), dv);
+    dv = fma(wv[t], M(1, s + t), dv);
     dw = fma(w[t], M(2, s + t), dw);
     if (d.heated) dt = fma(w[t], M(3, s + t), dt);
   }
@@ -128,7 +133,7 @@ __device__ void mean_row(const Dims &d, const Grid &g, const double2 *__restrict
   mean[6 * n + j] = dt;
 }
 
-template <typename T, int NF>
+template <typename T, int NF, bool PIPE = false>
 __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
                        C2<T> *__restrict__ Z, const TwT<T> *__restrict__ tw, int tm, int drop_mean,
                        double *__restrict__ mean) {
@@ -154,7 +159,7 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
     const int li = w.r;
     const int kk = w.c;
     const int k = kk - K;
-    const double2 v = derived(d, g, u, f, j, mt0 + li, kk, drop_mean != 0);
+    const double2 v = derived<PIPE>(d, g, u, f, j, mt0 + li, kk, drop_mean != 0);
     buf[li * ls + PD<T>((k >= 0 ? k : nz + k))] = {T(v.x), T(v.y)};
   }
   const int npad = nz - mz;
@@ -391,7 +396,7 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 //     every finite value, so the maximum also flags them), reduced across
 //     each wavefront by DPP.
 template <typename T, int N, int NI, int G, int SH>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(G == 64 ? kThetaWaveThreads : kFftThreads)
 k_theta_fx(Dims d, Grid g, const C2<T> *__restrict__ Z, C2<T> *__restrict__ W,
            const TwT<T> *__restrict__ tw, double dth, double dzs, double *__restrict__ cfl_part,
            int want_cfl, const double *__restrict__ mean) {
@@ -1025,10 +1030,11 @@ hipError_t zinv_impl(const nsc_ctx *c, const double *u, const T *tw) {
   const size_t shm = ((size_t)tm * lds_line<T>(c->d.nz) + tw_slots<T>(c->d.nz)) * sizeof(C2<T>);
   // FP32 1536-point lines: the fixed-length wavefront stages
   return with_fixed_len<sizeof(T) == 4>(c->d.nz, c->plan_z.wave_lines > 0, [&](auto nf) {
-    hipLaunchKernelGGL((k_zinv<T, decltype(nf)::value>), grid, dim3(threads), shm, c->stream,
-                       c->d, c->g, c->plan_z, reinterpret_cast<const double2 *>(u),
-                       reinterpret_cast<C2<T> *>(c->zbuf), reinterpret_cast<const TwT<T> *>(tw),
-                       tm, 1, c->s_mean);
+    constexpr int NF = decltype(nf)::value;
+    auto kern = c->d.pipe ? k_zinv<T, NF, true> : k_zinv<T, NF, false>;
+    hipLaunchKernelGGL(kern, grid, dim3(threads), shm, c->stream, c->d, c->g, c->plan_z,
+                       reinterpret_cast<const double2 *>(u), reinterpret_cast<C2<T> *>(c->zbuf),
+                       reinterpret_cast<const TwT<T> *>(tw), tm, 1, c->s_mean);
     return hipGetLastError();
   });
 }
@@ -1049,7 +1055,8 @@ FxLaunch fx_launch(const nsc_ctx *c, size_t esize, int np, int G, int SH) {
   const size_t tws = (size_t)nt * 16;
   FxLaunch L{0, dim3(1), 0};
   int best = 0;
-  for (int s = 1; s * G <= kFftThreads; ++s) {
+  const int maxt = G == 64 ? kThetaWaveThreads : kFftThreads;  // the kernel's launch bound
+  for (int s = 1; s * G <= maxt; ++s) {
     const size_t shm = tws + (size_t)s * np * line;
     if (shm > (size_t)c->lds_max) break;
     const int per_cu = (int)((size_t)c->lds_cu / shm) * s;

@@ -99,8 +99,12 @@ std::vector<double> remap_weights(const std::vector<double> &x0, const std::vect
   return W;
 }
 
+// The grid limits of nsc_init: N_r <= 4096 and padded lengths 3 M_theta,
+// 3 (M_z + 1) / 2 <= 4096.  They bound the payload (< 2^40 bytes), so a
+// header's sizes cannot wrap the byte count.
 bool valid_dims(int n_r, int m_theta, int m_z) {
-  return n_r >= kStencil && m_theta >= 1 && m_z >= 1 && (m_z & 1) == 1;
+  return n_r >= kStencil && n_r <= 4096 && m_theta >= 1 && 3 * (long)m_theta <= kMaxFFT &&
+         m_z >= 1 && (m_z & 1) == 1 && 3 * (((long)m_z - 1) / 2 + 1) <= kMaxFFT;
 }
 
 // State file: a 128-byte little-endian header, then the coefficients
@@ -177,6 +181,7 @@ using nsc::StateHeader;
 int nsc_remap_state(nsc_ctx *c, const double *src, int N_r_src, int M_theta_src, int M_z_src,
                     double *dst) {
   if (!c || !src || !dst || !nsc::valid_dims(N_r_src, M_theta_src, M_z_src)) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   const size_t sbytes = (size_t)c->d.f * N_r_src * M_theta_src * M_z_src * 2 * sizeof(double);
   const size_t dbytes = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2 * sizeof(double);
   const char *s0 = reinterpret_cast<const char *>(src), *d0 = reinterpret_cast<const char *>(dst);
@@ -201,6 +206,7 @@ int nsc_remap_state(nsc_ctx *c, const double *src, int N_r_src, int M_theta_src,
 
 int nsc_save_state(nsc_ctx *c, const double *u_hat, double time, const char *path) {
   if (!c || !u_hat || !path) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   StateHeader h{};
   std::memcpy(h.magic, nsc::kMagic, 8);
   h.version = nsc::kVersion;
@@ -257,6 +263,7 @@ int nsc_read_state_header(const char *path, int *dims, double *params) {
 
 int nsc_load_state(nsc_ctx *c, const char *path, double *u_hat, double *time_out) {
   if (!c || !path || !u_hat) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   FILE *fp = std::fopen(path, "rb");
   if (!fp) return NSC_ERR_IO;
   StateHeader h{};

@@ -36,17 +36,21 @@ __device__ __forceinline__ Cd ld(const double2 *p) {
 __device__ __forceinline__ void st(double2 *p, Cd v) { *p = make_double2(v.x, v.y); }
 __device__ __forceinline__ Cd fmac(double w, Cd v, Cd acc) { return {fma(w, v.x, acc.x), fma(w, v.y, acc.y)}; }
 
-// Matrix entry A[i][c] of an operator for c in the window of row i.
+// Matrix entry A[i][c] of an operator for c in the window of row i.  pipe:
+// row 0 is an inner row (the axis is no boundary) and the derivative rows
+// are those of the operator's parity (off: their element offset).
 struct OpRow {
   int kind;
   double alpha, beta, q2, k2;
+  int pipe, off;
   __device__ __forceinline__ void row(const Grid &g, int n, int i, double *a, int &s) const {
     s = g.s[i];
-    const double *w1 = g.d1 + i * kStencil;
-    const double *w2 = g.d2 + i * kStencil;
+    const double *w1 = g.d1 + off + i * kStencil;
+    const double *w2 = g.d2 + off + i * kStencil;
     const double ri = g.rinv[i];
+    const bool inner_wall = i == 0 && !pipe;
     if (kind == OP_HELMHOLTZ) {
-      if (i == 0 || i == n - 1) {
+      if (inner_wall || i == n - 1) {
 #pragma unroll
         for (int t = 0; t < kStencil; ++t) a[t] = (s + t == i) ? 1.0 : 0.0;
         return;
@@ -58,7 +62,7 @@ struct OpRow {
         a[t] = v;
       }
     } else if (kind == OP_POISSON) {
-      if (i == 0 || i == n - 1) {
+      if (inner_wall || i == n - 1) {
 #pragma unroll
         for (int t = 0; t < kStencil; ++t) a[t] = w1[t];
         return;
@@ -70,9 +74,10 @@ struct OpRow {
         a[t] = v;
       }
     } else {  // mean pressure head: (D2 + D1/r) p inside, p(r_i) = 0, D1 row at r_o
-      if (i == 0) {
+              // (pipe: p = 0 at the wall, the axis no boundary)
+      if (inner_wall || (pipe && i == n - 1)) {
 #pragma unroll
-        for (int t = 0; t < kStencil; ++t) a[t] = (s + t == 0) ? 1.0 : 0.0;
+        for (int t = 0; t < kStencil; ++t) a[t] = (s + t == i) ? 1.0 : 0.0;
         return;
       }
       if (i == n - 1) {
@@ -108,7 +113,7 @@ k_factor(Dims d, Grid g, Factors F0, Factors F1, int kind, double alpha, double 
   const int q = op / kp1 + q_off;
   const int ka = op - (op / kp1) * kp1;
   const double kap = (double)ka * d.kz;
-  OpRow R{kind, alpha, beta, (double)q * (double)q, kap * kap};
+  OpRow R{kind, alpha, beta, (double)q * (double)q, kap * kap, d.pipe, odd_off(g, q)};
   const size_t nops = F.nops;
   // the pure-Neumann Poisson operator of (q = 0, kappa = 0) is singular and
   // never used; its slot holds the mean pressure-head operator instead
@@ -266,9 +271,10 @@ struct Rd {
 __device__ __forceinline__ Rd operator-(Rd a, Rd b) { return {a.v - b.v}; }
 __device__ __forceinline__ Rd operator*(double s, Rd a) { return {s * a.v}; }
 
-__device__ __forceinline__ double d1_row(const Grid &g, int j, const double *x, size_t stride) {
+__device__ __forceinline__ double d1_row(const Grid &g, int j, const double *x, size_t stride,
+                                        int off = 0) {
   const int s = g.s[j];
-  const double *w = g.d1 + j * kStencil;
+  const double *w = g.d1 + off + j * kStencil;
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < kStencil; ++t) acc = fma(w[t], x[(size_t)(s + t) * stride], acc);
@@ -321,10 +327,10 @@ __global__ void __launch_bounds__(64) k_influence_x(Dims d, Grid g, Factors fv, 
   // X+ = H_{m+1}^-1 (-(D1 p - m p / r)), X- = H_{|m-1|}^-1 (-(D1 p + m p / r)),
   // h = H_m^-1 p so that X_z = -i kappa h
   auto rhs = [&](int j, const double *p, size_t stride) {
-    if (j == 0 || j == n - 1) return Rd{0.0};
+    if ((j == 0 && !d.pipe) || j == n - 1) return Rd{0.0};
     const double pj = p[(size_t)j * stride];
     if (kind == 2) return Rd{pj};
-    const double dp = d1_row(g, j, p, stride);
+    const double dp = d1_row(g, j, p, stride, odd_off(g, m));  // p of order m
     const double mp = mm * g.rinv[j] * pj;
     return Rd{kind == 0 ? -(dp - mp) : -(dp + mp)};
   };
@@ -361,15 +367,22 @@ __global__ void __launch_bounds__(64) k_influence_a(Dims d, Grid g, Influence I)
   const double mm = (double)m;
   // A[w][jj] = wall divergence of response jj (walls carry zero velocity)
   double A[2][2];
+  const int off = odd_off(g, m + 1);  // X+- of orders m +- 1
   for (int jj = 0; jj < 2; ++jj) {
     const double *Xp = I.resp + (size_t)(2 + jj) * n * ns + op;
     const double *Xm = I.resp + (size_t)(4 + jj) * n * ns + op;
     for (int w = 0; w < 2; ++w) {
       const int j = w == 0 ? 0 : n - 1;
       const double ri = g.rinv[j];
-      A[w][jj] = 0.5 * ((d1_row(g, j, Xp, ns) + (1.0 + mm) * ri * Xp[(size_t)j * ns]) +
-                        (d1_row(g, j, Xm, ns) + (1.0 - mm) * ri * Xm[(size_t)j * ns]));
+      A[w][jj] = 0.5 * ((d1_row(g, j, Xp, ns, off) + (1.0 + mm) * ri * Xp[(size_t)j * ns]) +
+                        (d1_row(g, j, Xm, ns, off) + (1.0 - mm) * ri * Xm[(size_t)j * ns]));
     }
+  }
+  if (d.pipe) {
+    // one wall: the first condition becomes lambda_1 = 0 (k_influence gives
+    // it a zero right side), the second is the wall's
+    A[0][0] = 1.0;
+    A[0][1] = 0.0;
   }
   const double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
   I.ainv[0 * ns + op] = A[1][1] / det;
@@ -444,7 +457,7 @@ __device__ __forceinline__ void stencil_rows(const Grid &g, const double *__rest
 // blockIdx.z: 0 the +- pair (from u_r, u_theta), 1 u_z, 2 T -- one stencil
 // family per thread keeps the registers (and so the occupancy) of a
 // memory-bound kernel moderate.  blockIdx.y: a chunk of R rows per lane.
-template <int R>
+template <int R, bool PIPE = false>
 __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__restrict__ u,
                       const double2 *__restrict__ nn, const double2 *__restrict__ nq,
                       double2 *__restrict__ sf, double idt, double cc, int rows_first) {
@@ -468,9 +481,10 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
     return cc * ld(nq + o) + ce * ld(nn + o);
   };
   if (part == 0) {
-    // stencil sums of (D2 + D1/r) applied to u_r and u_theta
+    // stencil sums of (D2 + D1/r) applied to u_r and u_theta (pipe: the
+    // rows of parity (-1)^(m+1), per lane)
     Cd l[2][R], x[2][R];
-    stencil_rows<R, 2>(g, g.lw, n, j0, nrow, u + md, fs, P, l, x);
+    stencil_rows<R, 2>(g, PIPE ? g.lw + odd_off(g, m + 1) : g.lw, n, j0, nrow, u + md, fs, P, l, x);
     const double qp = (double)(m + 1), qm = (double)(m >= 1 ? m - 1 : 1 - m);
 #pragma unroll
     for (int jj = 0; jj < R; ++jj) {
@@ -492,7 +506,8 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
     // u_z (operator L_m) or T (L_m / Pr)
     const int f = part + 1;
     Cd l[1][R], x[1][R];
-    stencil_rows<R, 1>(g, g.lw, n, j0, nrow, u + f * fs + md, fs, P, l, x);
+    stencil_rows<R, 1>(g, PIPE ? g.lw + odd_off(g, m) : g.lw, n, j0, nrow, u + f * fs + md, fs, P,
+                       l, x);
     const double cf = f == 3 ? ce / d.pr : ce;
 #pragma unroll
     for (int jj = 0; jj < R; ++jj) {
@@ -757,7 +772,7 @@ k_sweep(Dims d, SweepArgs a) {
 // Velocity right sides in place of f: f_X - (grad p0)_X inside, wall values
 // on rows 0 and N-1; mode (0,0) solves u_theta directly (X+- = +-i u_theta).
 // R consecutive rows per lane (blockIdx.y: the chunk).
-template <int R>
+template <int R, bool PIPE = false>
 __global__ void __launch_bounds__(256)
 k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ sp, int walls,
           int rows_first) {
@@ -786,24 +801,26 @@ k_vel_rhs(Dims d, Grid g, double2 *__restrict__ sf, const double2 *__restrict__ 
   if (zero) {
     for (int jj = 0; jj < nrow; ++jj) {
       const int j = j0 + jj;
-      if (j == 0 || j == n - 1) {
+      if ((j == 0 && !PIPE) || j == n - 1) {
         wall_row(j);
         continue;
       }
       const Cd h = 0.5 * (ld(field(0, j)) - ld(field(1, j)));
       st(field(0, j), h);
       st(field(1, j), Cd{-h.x, -h.y});
+      // pipe: the driving pressure gradient in the axial mean flow
+      if (PIPE && walls) st(field(2, j), ld(field(2, j)) + Cd{d.gp, 0.0});
     }
     return;
   }
   const double kap = (double)(kk - d.kmax) * d.kz;
   Cd dp[1][R], pc[1][R];
-  stencil_rows<R, 1>(g, g.d1, n, j0, nrow, sp + md, 0, P, dp, pc);
+  stencil_rows<R, 1>(g, PIPE ? g.d1 + odd_off(g, m) : g.d1, n, j0, nrow, sp + md, 0, P, dp, pc);
 #pragma unroll
   for (int jj = 0; jj < R; ++jj) {
     if (jj >= nrow) break;
     const int j = j0 + jj;
-    if (j == 0 || j == n - 1) {
+    if ((j == 0 && !PIPE) || j == n - 1) {
       wall_row(j);
       continue;
     }
@@ -833,8 +850,9 @@ __device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *_
     st(sf + ((size_t)3 * n + j) * P + md, Cd{mean ? (j == 0 ? 0.5 : -0.5) : 0.0, 0.0});
   }
   if (md == d.kmax) {
+    // (pipe: every row but the wall's, where p = 0; F_r odd in r)
     Cd r = {0, 0};
-    if (want_p && nn && j > 0) {
+    if (want_p && nn && (j > 0 || d.pipe) && !(d.pipe && j == n - 1)) {
       auto Fr = [&](int t) {
         return cc * ld(nq + (size_t)t * P + md) + (1.0 - cc) * ld(nn + (size_t)t * P + md);
       };
@@ -842,7 +860,7 @@ __device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *_
         r = Fr(n - 1);
       } else {
         const int s0 = g.s[j];
-        const double *w = g.d1 + j * kStencil;
+        const double *w = g.d1 + g.podd + j * kStencil;
         r = g.rinv[j] * Fr(j);
         for (int t = 0; t < kStencil; ++t) r = fmac(w[t], Fr(s0 + t), r);
       }
@@ -858,7 +876,7 @@ __device__ __forceinline__ void div_row(const Dims &d, const Grid &g, double2 *_
 // and F_- that the rows' nine-point windows share are read once (R + 8 rows
 // for R outputs inside, fewer at the walls) instead of nine times, and each
 // derivative still sums its window from the left, as a single row would.
-template <int R>
+template <int R, bool PIPE = false>
 __global__ void __launch_bounds__(256)
 k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
        const double2 *__restrict__ nn, const double2 *__restrict__ nq, double cc, int want_p,
@@ -881,12 +899,13 @@ k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
   const double2 *fz = sf + (size_t)2 * n * P + md;
   // D1 of F_+ and F_- (fields 0 and 1 of f)
   Cd dv[2][R], v[2][R];
-  stencil_rows<R, 2>(g, g.d1, n, j0, nrow, sf + md, (size_t)n * P, P, dv, v);
+  stencil_rows<R, 2>(g, PIPE ? g.d1 + odd_off(g, m + 1) : g.d1, n, j0, nrow, sf + md,
+                     (size_t)n * P, P, dv, v);
 #pragma unroll
   for (int jj = 0; jj < R; ++jj) {
     const int j = j0 + jj;
     if (jj >= nrow) break;
-    if (j == 0 || j == n - 1) {
+    if ((j == 0 && !PIPE) || j == n - 1) {
       div_row(d, g, sf, sg, nn, nq, cc, want_p, walls, md, j);
       continue;
     }
@@ -902,6 +921,7 @@ k_div2(Dims d, Grid g, double2 *__restrict__ sf, double2 *__restrict__ sg,
 // One lane per mode, 64-lane workgroups (more of the chip for a small
 // grid); the wall windows start at 0 and N-9, so all 38 loads of a lane are
 // independent and issue together.
+template <bool PIPE = false>
 __global__ void __launch_bounds__(64) k_influence(Dims d, Grid g, Influence I,
                                                   const double2 *__restrict__ sx,
                                                   double2 *__restrict__ lam) {
@@ -921,12 +941,13 @@ __global__ void __launch_bounds__(64) k_influence(Dims d, Grid g, Influence I,
   const double kap = (double)(kk - d.kmax) * d.kz;
   const double mm = (double)m;
   const double2 *xp = sx + md, *xm = sx + (size_t)n * P + md, *xz = sx + (size_t)2 * n * P + md;
-  Cd beta[2];
+  Cd beta[2] = {Cd{0, 0}, Cd{0, 0}};
 #pragma unroll
-  for (int w = 0; w < 2; ++w) {
+  for (int w = PIPE ? 1 : 0; w < 2; ++w) {  // (pipe: one wall, beta[0] = 0)
     const int j = w == 0 ? 0 : n - 1;
     const int s0 = w == 0 ? 0 : n - kStencil;  // one-sided wall window
     const double *wd = g.d1 + j * kStencil;
+    if constexpr (PIPE) wd += odd_off(g, m + 1);
     const double ri = g.rinv[j];
     Cd dp = {0.0, 0.0}, dm = {0.0, 0.0};
 #pragma unroll
@@ -1098,6 +1119,35 @@ __global__ void k_seed(Dims d, Grid g, const double2 *__restrict__ amps, double2
   }
   if (md == d.kmax) a = {0, 0};
   const double r = g.r[j];
+  if (d.pipe) {
+    // u_+- = (a_r +- i a_theta) g_{m+-1}, u_z = a_z g_m, g_q = r^q (1 - r^2)^2
+    // at peak one (regular at the axis); this lane writes component f
+    const int m = md / d.mz;
+    auto gq = [&](int q) {
+      const double w = 1.0 - r * r;
+      const double peak = q > 0 ? pow(q / (q + 4.0), 0.5 * q) * (16.0 / ((q + 4.0) * (q + 4.0))) : 1.0;
+      return pow(r, (double)q) * w * w / peak;
+    };
+    Cd v;
+    if (f == 2) {
+      v = gq(m) * a;
+    } else {
+      // both in-plane amplitudes, the m = 0 column made Hermitian
+      Cd ar = ld(amps + md), at = ld(amps + P + md);
+      if (md < d.mz) {
+        const int mm = d.mz - 1 - md;
+        const Cd br = ld(amps + mm), bt = ld(amps + P + mm);
+        ar = {0.5 * (ar.x + br.x), 0.5 * (ar.y - br.y)};
+        at = {0.5 * (at.x + bt.x), 0.5 * (at.y - bt.y)};
+      }
+      if (md == d.kmax) ar = at = Cd{0, 0};
+      const Cd up = gq(m + 1) * (ar + ci(at));
+      const Cd um = gq(m >= 1 ? m - 1 : 1 - m) * (ar - ci(at));
+      v = f == 0 ? 0.5 * (up + um) : Cd{0.5 * (up.y - um.y), -0.5 * (up.x - um.x)};
+    }
+    st(out + ((size_t)f * d.nr + j) * P + md, v);
+    return;
+  }
   const double s = 16.0 * (r - d.r_i) * (r - d.r_i) * (d.r_o - r) * (d.r_o - r);
   st(out + ((size_t)f * d.nr + j) * P + md, s * a);
 }
@@ -1109,7 +1159,10 @@ __global__ void k_add_base(Dims d, Grid g, const double2 *__restrict__ pert, dou
   if (md >= d.nmodes) return;
   const size_t P = d.nmodes;
   const double r = g.r[j];
-  if (md == d.kmax) {
+  if (md == d.kmax && d.pipe) {  // Hagen--Poiseuille flow Re (1 - r^2), Re = gp / 4
+    double2 *p = out + ((size_t)2 * d.nr + j) * P + md;
+    p->x += 0.25 * d.gp * (1.0 - r * r);
+  } else if (md == d.kmax) {
     double2 *p = out + ((size_t)1 * d.nr + j) * P + md;
     p->x += d.a_cou * r + d.b_cou * g.rinv[j];
   }
@@ -1794,7 +1847,8 @@ hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const
   const int parts = c->d.heated ? 3 : 2;
   auto rhs = [&](auto rows) {
     constexpr int R = decltype(rows)::value;
-    hipLaunchKernelGGL((k_rhs<R>), mode_grid(c, (c->d.nr + R - 1) / R, parts), dim3(256), 0,
+    auto kern = c->d.pipe ? k_rhs<R, true> : k_rhs<R, false>;
+    hipLaunchKernelGGL(kern, mode_grid(c, (c->d.nr + R - 1) / R, parts), dim3(256), 0,
                        c->stream, c->d, c->g, reinterpret_cast<const double2 *>(u),
                        reinterpret_cast<const double2 *>(nn), reinterpret_cast<const double2 *>(nq),
                        reinterpret_cast<double2 *>(c->s_f), 1.0 / dt, cc, c->rows_first);
@@ -1808,7 +1862,8 @@ hipError_t launch_rhs(const nsc_ctx *c, const double *u, const double *nn, const
 }
 
 hipError_t launch_influence(const nsc_ctx *c) {
-  hipLaunchKernelGGL(k_influence, dim3((c->d.nmodes + 63) / 64), dim3(64), 0, c->stream, c->d, c->g, c->inf,
+  auto kern = c->d.pipe ? k_influence<true> : k_influence<false>;
+  hipLaunchKernelGGL(kern, dim3((c->d.nmodes + 63) / 64), dim3(64), 0, c->stream, c->d, c->g, c->inf,
                      reinterpret_cast<const double2 *>(c->s_x), reinterpret_cast<double2 *>(c->s_lam));
   return hipGetLastError();
 }
@@ -1945,7 +2000,8 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   if (stage == 0) {
     auto div = [&](auto rows) {
       constexpr int R = decltype(rows)::value;
-      hipLaunchKernelGGL((k_div2<R>), mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0, c->stream,
+      auto kern = d.pipe ? k_div2<R, true> : k_div2<R, false>;
+      hipLaunchKernelGGL(kern, mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0, c->stream,
                          d, c->g, sf, sg, reinterpret_cast<const double2 *>(nn),
                          reinterpret_cast<const double2 *>(nq), cc, wp, walls, c->rows_first);
     };
@@ -1963,7 +2019,8 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   } else if (stage == 2) {
     auto vel = [&](auto rows) {
       constexpr int R = decltype(rows)::value;
-      hipLaunchKernelGGL((k_vel_rhs<R>), mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0,
+      auto kern = d.pipe ? k_vel_rhs<R, true> : k_vel_rhs<R, false>;
+      hipLaunchKernelGGL(kern, mode_grid(c, (d.nr + R - 1) / R), dim3(256), 0,
                          c->stream, d, c->g, sf, sp, walls, c->rows_first);
     };
     switch (chunk_rows(c, 1, 8)) {

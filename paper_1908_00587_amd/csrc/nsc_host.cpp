@@ -273,6 +273,7 @@ int pending_nonfinite(nsc_ctx *c) {
 int nsc::step_vjp_check(const nsc_ctx *c, const double *u, const double *stages,
                         const double *ubar_next, const double *ubar) {
   if (!c || !u || !stages || !ubar_next || !ubar) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)ubar_next)
     return NSC_ERR_ARG;
   const size_t fld = (size_t)c->d.f * c->d.nr * c->d.nmodes * 2;
@@ -349,8 +350,10 @@ int nsc_destroy(nsc_ctx *c) {
   return NSC_OK;
 }
 
+// pipe = 1: the pipe-flow variant (eta, Re_o, Ra, Pr unused; Re_i is the
+// centreline speed Re of the laminar flow).
 static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra, double Pr,
-                     int N_r, int M_theta, int M_z, double L_z) {
+                     int N_r, int M_theta, int M_z, double L_z, int pipe = 0) {
   Dims &d = c->d;
   d.nr = N_r;
   d.mt = M_theta;
@@ -371,6 +374,16 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   d.lz = L_z;
   d.a_cou = (Re_o * d.r_o - Re_i * d.r_i) / (d.r_o * d.r_o - d.r_i * d.r_i);
   d.b_cou = d.r_i * (Re_i - d.a_cou * d.r_i);
+  d.pipe = pipe;
+  d.gp = 0.0;
+  if (pipe) {
+    // radius 1, no wall motion, driven by -dP/dz = 4 Re (laminar: Re (1 - r^2))
+    d.re_i = d.re_o = 0.0;
+    d.r_i = 0.0;
+    d.r_o = 1.0;
+    d.a_cou = d.b_cou = 0.0;
+    d.gp = 4.0 * Re_i;
+  }
   c->eta = eta;
   c->ra = Ra;
   c->n_in = d.heated ? 9 : 6;
@@ -411,11 +424,19 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   const int n = d.nr;
   c->h_r = new (std::nothrow) double[n];
   if (!c->h_r) return NSC_ERR_OOM;
-  std::vector<double> rinv(n), d1(n * kStencil), d2(n * kStencil), dr(n), ccw(n);
+  // np parity sets of derivative rows: one for the cylinders, two (even,
+  // odd) for the pipe
+  const int np = pipe ? 2 : 1;
+  const int nw = n * kStencil;
+  std::vector<double> rinv(n), d1(np * nw), d2(np * nw), dr(n), ccw(n, 0.0);
   std::vector<int> s(n);
   for (int j = 0; j < n; ++j) {
-    const double x = std::cos(M_PI * (double)(n - 1 - j) / (double)(n - 1));
-    c->h_r[j] = 0.5 * (d.r_i + d.r_o) + 0.5 * x;
+    if (pipe) {  // positive half of the 2 N_r Gauss--Lobatto points of [-1, 1]
+      c->h_r[j] = std::cos(M_PI * (double)(n - 1 - j) / (double)(2 * n - 1));
+    } else {
+      const double x = std::cos(M_PI * (double)(n - 1 - j) / (double)(n - 1));
+      c->h_r[j] = 0.5 * (d.r_i + d.r_o) + 0.5 * x;
+    }
   }
   for (int j = 0; j < n; ++j) {
     rinv[j] = 1.0 / c->h_r[j];
@@ -424,38 +445,69 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
     if (sj > n - kStencil) sj = n - kStencil;
     s[j] = sj;
     double w[kStencil * 3];
-    fd_weights(c->h_r[j], c->h_r + sj, kStencil, w);
-    for (int t = 0; t < kStencil; ++t) {
-      d1[j * kStencil + t] = w[t * 3 + 1];
-      d2[j * kStencil + t] = w[t * 3 + 2];
+    if (!pipe) {
+      fd_weights(c->h_r[j], c->h_r + sj, kStencil, w);
+      for (int t = 0; t < kStencil; ++t) {
+        d1[j * kStencil + t] = w[t * 3 + 1];
+        d2[j * kStencil + t] = w[t * 3 + 2];
+      }
+    } else {
+      // the nine points nearest to r_j on the grid extended by the mirror
+      // points -r_k (position N_r + j of 2 N_r, ascending); a mirror point's
+      // weight goes to column k times the parity (+1 even, -1 odd)
+      double x[kStencil];
+      const int e0 = n + j;
+      int se = e0 - kHalf;
+      if (se > 2 * n - kStencil) se = 2 * n - kStencil;
+      for (int t = 0; t < kStencil; ++t) {
+        const int e = se + t;
+        x[t] = e >= n ? c->h_r[e - n] : -c->h_r[n - 1 - e];
+      }
+      fd_weights(c->h_r[j], x, kStencil, w);
+      for (int par = 0; par < 2; ++par) {
+        const double sg = par ? -1.0 : 1.0;
+        for (int t = 0; t < kStencil; ++t) {
+          const int e = se + t;
+          const int col = e >= n ? e - n : n - 1 - e;
+          const double f = e >= n ? 1.0 : sg;
+          d1[par * nw + j * kStencil + col - sj] += f * w[t * 3 + 1];
+          d2[par * nw + j * kStencil + col - sj] += f * w[t * 3 + 2];
+        }
+      }
     }
-    const double lo = j > 0 ? c->h_r[j] - c->h_r[j - 1] : c->h_r[1] - c->h_r[0];
+    double lo = j > 0 ? c->h_r[j] - c->h_r[j - 1] : c->h_r[1] - c->h_r[0];
+    if (pipe && j == 0) lo = 2.0 * c->h_r[0];  // the mirror point -r_0
     const double hi = j < n - 1 ? c->h_r[j + 1] - c->h_r[j] : c->h_r[n - 1] - c->h_r[n - 2];
     dr[j] = lo < hi ? lo : hi;
   }
-  cc_weights_host(n, ccw.data());
-  for (int j = 0; j < n; ++j) ccw[j] *= 0.5;
-  std::vector<double> lw(n * kStencil);
-  for (int j = 0; j < n; ++j)
-    for (int t = 0; t < kStencil; ++t)
-      lw[j * kStencil + t] = std::fma(d1[j * kStencil + t], rinv[j], d2[j * kStencil + t]);
+  if (!pipe) {
+    cc_weights_host(n, ccw.data());
+    for (int j = 0; j < n; ++j) ccw[j] *= 0.5;
+  }
+  std::vector<double> lw(np * nw);
+  for (int par = 0; par < np; ++par)
+    for (int j = 0; j < n; ++j)
+      for (int t = 0; t < kStencil; ++t) {
+        const int i = par * nw + j * kStencil + t;
+        lw[i] = std::fma(d1[i], rinv[j], d2[i]);
+      }
   // device tables: one allocation
-  const size_t nd = (size_t)n * (1 + 1 + kStencil * 3 + 1 + 1);
+  const size_t nd = (size_t)n * (1 + 1 + 1 + 1) + (size_t)np * nw * 3;
   TRY(dmalloc(&c->tables, nd * sizeof(double) + (size_t)n * sizeof(int) + 256));
   double *base = (double *)c->tables;
-  double *p_r = base, *p_rinv = p_r + n, *p_d1 = p_rinv + n, *p_d2 = p_d1 + n * kStencil,
-         *p_dr = p_d2 + n * kStencil, *p_cc = p_dr + n;
+  double *p_r = base, *p_rinv = p_r + n, *p_d1 = p_rinv + n, *p_d2 = p_d1 + np * nw,
+         *p_dr = p_d2 + np * nw, *p_cc = p_dr + n;
   double *p_lw = p_cc + n;
-  int *p_s = (int *)(p_lw + n * kStencil);
+  int *p_s = (int *)(p_lw + np * nw);
   HIPCHK(hipMemcpy(p_r, c->h_r, n * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_rinv, rinv.data(), n * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(p_d1, d1.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(p_d2, d2.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_d1, d1.data(), np * nw * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_d2, d2.data(), np * nw * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_dr, dr.data(), n * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_cc, ccw.data(), n * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(p_lw, lw.data(), n * kStencil * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p_lw, lw.data(), np * nw * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_s, s.data(), n * sizeof(int), hipMemcpyHostToDevice));
-  c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc, p_lw};
+  c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc, p_lw, pipe ? nw : 0};
 
   // twiddles
   {
@@ -540,6 +592,24 @@ int nsc_init(double eta, double Re_i, double Re_o, double Ra, double Pr, int N_r
   return NSC_OK;
 }
 
+int nsc_init_pipe(double Re, int N_r, int M_theta, int M_z, double L_z, nsc_ctx **out) {
+  if (!out) return NSC_ERR_ARG;
+  *out = nullptr;
+  if (!std::isfinite(Re)) return NSC_ERR_ARG;
+  // the cylinder checks with a dummy radius ratio cover the grid sizes
+  int st = validate(0.5, Re, 0.0, 0.0, 1.0, N_r, M_theta, M_z, L_z);
+  if (st != NSC_OK) return st;
+  nsc_ctx *c = new (std::nothrow) nsc_ctx();
+  if (!c) return NSC_ERR_OOM;
+  st = init_impl(c, 0.5, Re, 0.0, 0.0, 1.0, N_r, M_theta, M_z, L_z, 1);
+  if (st != NSC_OK) {
+    nsc_destroy(c);
+    return st;
+  }
+  *out = c;
+  return NSC_OK;
+}
+
 int nsc_set_stream(nsc_ctx *c, void *s) {
   if (!c) return NSC_ERR_ARG;
   c->stream = (hipStream_t)s;
@@ -615,6 +685,7 @@ int nsc_step(nsc_ctx *c, double *u, double *dt_inout) {
 
 int nsc_energy(nsc_ctx *c, const double *u, double *e_dev) {
   if (!c || !u || !e_dev) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   HIPCHK(launch_energy(c, u, e_dev));
   return NSC_OK;
 }
@@ -629,6 +700,7 @@ int nsc_initial_state(nsc_ctx *c, const double *amps, double *out) {
 
 int nsc_nonlinear_vjp(nsc_ctx *c, const double *u, const double *nbar, double *ubar) {
   if (!c || !u || !nbar || !ubar) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   if ((const void *)ubar == (const void *)u || (const void *)ubar == (const void *)nbar)
     return NSC_ERR_ARG;
   if (!theta_fits(c, c->precision, 1)) return NSC_ERR_STATE;
@@ -639,6 +711,7 @@ int nsc_nonlinear_vjp(nsc_ctx *c, const double *u, const double *nbar, double *u
 int nsc_radial_solve_vjp(nsc_ctx *c, const double *ubar_out, double *ubar_n, double *nbar_n,
                          double *nbar_q) {
   if (!c || !ubar_out || !ubar_n || !nbar_n || !nbar_q) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   const void *o = ubar_out;
   if (o == ubar_n || o == nbar_n || o == nbar_q || (void *)ubar_n == (void *)nbar_n ||
       (void *)ubar_n == (void *)nbar_q || (void *)nbar_n == (void *)nbar_q)
@@ -680,6 +753,7 @@ int nsc_step_vjp(nsc_ctx *c, const double *u, const double *stages, const double
 
 int nsc_energy_grad(nsc_ctx *c, const double *u, double *g) {
   if (!c || !u || !g || (const void *)u == (const void *)g) return NSC_ERR_ARG;
+  if (c->d.pipe) return NSC_ERR_STATE;
   HIPCHK(launch_energy_grad(c, u, g));
   return NSC_OK;
 }

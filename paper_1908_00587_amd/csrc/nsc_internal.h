@@ -40,13 +40,23 @@ struct Grid {
   const double *dr;    // [N_r] local spacing for the CFL bound
   const double *ccw;   // [N_r] Clenshaw--Curtis weights on [r_i, r_o]
   const double *lw;    // [N_r][9] weights of D2 + D1/r (fma(d1, 1/r, d2))
+  // pipe: d1, d2 and lw hold a second set of rows for functions odd in r
+  // (mirror points folded with the sign -1) at this element offset; 0 for
+  // the cylinders, whose rows do not depend on a parity
+  int podd;
 };
 
 // Problem sizes and physical constants passed by value to kernels.
 struct Dims {
   int nr, mt, mz, kmax, nt, nz, nmodes, f, heated;
   double kz, gr, pr, re_i, re_o, a_cou, b_cou, r_i, r_o, lz;
+  int pipe;   // 1: pipe flow (axis at r = 0, wall at r = 1), 0: two cylinders
+  double gp;  // pipe: the driving mean pressure gradient -dP/dz = 4 Re
 };
+
+// Parity of an order-q radial function of the pipe (odd q: odd in r); the
+// cylinders have a single set of rows.
+__host__ __device__ __forceinline__ int odd_off(const Grid &g, int q) { return (q & 1) ? g.podd : 0; }
 
 // Compact no-pivot LU factors of a family of radial operators.
 // vals: [N_r][kSlots][nops], edge: [kEdge][nops]; op = q * (K+1) + |k|.

@@ -33,7 +33,23 @@ WORKLOADS = {
     "tc-conv-n256": dict(eta=0.5, Re_i=1000.0, Re_o=0.0, Ra=1.0e6, Pr=0.7, N_r=256,
                          M_theta=512, M_z=1023, L_z=TWO_PI, amp=1e-3, amp_T=1e-3, dt=1e-3,
                          dynamic=True, steps=100, seed=1004),
+    # pipe flow (nsc_init_pipe): centreline speed Re = 4000 of the laminar
+    # flow, 64 points axis to wall, 64 x 127 modes -> 192 x 192, period
+    # 4 pi (about six diameters), CFL 0.5
+    "pipe-n64": dict(geometry="pipe", Re=4000.0, Ra=0.0, N_r=64, M_theta=64, M_z=127,
+                     L_z=2 * TWO_PI, amp=1.0, amp_T=0.0, dt=1e-4, dynamic=True, steps=200,
+                     seed=1005),
 }
+
+
+def is_pipe(name):
+    return WORKLOADS[name].get("geometry") == "pipe"
+
+
+def pipe_params(name):
+    """(Re, N_r, M_theta, M_z, L_z) of a pipe workload (nsc_init_pipe)."""
+    w = WORKLOADS[name]
+    return (w["Re"], w["N_r"], w["M_theta"], w["M_z"], w["L_z"])
 
 
 def params(name):

@@ -128,7 +128,7 @@ def test_state_header_roundtrip(tmp_path):
 
 
 @pytest.mark.parametrize("bad", ["missing", "magic", "version", "truncated", "long", "fields",
-                                 "even_mz", "small_nr"])
+                                 "even_mz", "small_nr", "large_nr", "wrapped"])
 def test_state_header_rejects(tmp_path, bad):
     from paper_1908_00587_amd import NscError, read_state_header
     from paper_1908_00587_amd._lib import NSC_ERR_IO
@@ -147,6 +147,11 @@ def test_state_header_rejects(tmp_path, bad):
         _write_state(p, dims=(12, 3, 4), payload=bytes(4 * 12 * 3 * 4 * 16))
     elif bad == "small_nr":
         _write_state(p, dims=(8, 3, 5), payload=bytes(4 * 8 * 3 * 5 * 16))
+    elif bad == "large_nr":
+        _write_state(p, dims=(4097, 1, 1), payload=bytes(4 * 4097 * 16))
+    elif bad == "wrapped":
+        # 4 * 2^29 * 2^29 * 1 * 16 bytes = 2^64: wraps to an empty payload
+        _write_state(p, dims=(1 << 29, 1 << 29, 1), payload=b"")
     with pytest.raises(NscError) as e:
         read_state_header(p)
     assert e.value.code == NSC_ERR_IO
