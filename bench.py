@@ -80,12 +80,16 @@ def kernel_bytes(name, w, prec):
     return 0
 
 
-# device kernel behind each timed solve stage of the default workload (the
-# transform kernels depend on the grid: _kernel_name)
-DEVICE_KERNEL = {"rhs": "nsc::k_rhs<4>", "div": "nsc::k_div2<2>",
-                 "sweep_pt": "nsc::k_sweep<true, 0, 64>", "sweep_vel": "nsc::k_sweep<true, 1, 64>",
-                 "vel_rhs": "nsc::k_vel_rhs<1>", "finalize": "nsc::k_finalize<false>",
-                 "influence": "nsc::k_influence"}
+# device kernels behind each timed stage in mixed precision, by name prefix
+# (template arguments depend on the grid and geometry: transform lengths,
+# field counts, line-set shapes, the LDS or global-memory sweep)
+STAGE_KERNELS = {"theta": ("nsc::k_theta<float,", "nsc::k_theta_fx<float,"),
+                 "zinv": ("nsc::k_zinv<float,",), "zfwd": ("nsc::k_zfwd<float,",),
+                 "rhs": ("nsc::k_rhs<",), "div": ("nsc::k_div2<",),
+                 "sweep_pt": ("nsc::k_sweep<true, 0,", "nsc::k_sweep<false, 0,"),
+                 "sweep_vel": ("nsc::k_sweep<true, 1,", "nsc::k_sweep<false, 1,"),
+                 "vel_rhs": ("nsc::k_vel_rhs<",), "finalize": ("nsc::k_finalize<false>",),
+                 "influence": ("nsc::k_influence<",)}
 
 
 def source_digest():
@@ -101,15 +105,16 @@ def source_digest():
     return h.hexdigest()
 
 
-def committed_traffic(wname, stage, w):
-    """HBM bytes per launch of a stage's kernel from the committed counter
-    summary profiles/hbm-traffic_<workload>.txt (FETCH_SIZE + WRITE_SIZE,
-    each scaled by the calibration kernel's reading), or None when the file
-    is missing or the kernel sources changed since it was taken."""
+def committed_traffic(wname, stage):
+    """(device kernel, HBM bytes per launch) of a stage from the committed
+    counter summary profiles/hbm-traffic_<workload>.txt (FETCH_SIZE +
+    WRITE_SIZE, each scaled by the calibration kernel's reading); bytes None
+    when the file is missing, the kernel sources changed since it was taken,
+    or no single kernel of the file matches the stage."""
     path = os.path.join(ROOT, "profiles", f"hbm-traffic_{wname}.txt")
-    name = _kernel_name(stage, w)
-    if name is None or not os.path.exists(path):
-        return None
+    prefixes = STAGE_KERNELS.get(stage, ())
+    if not prefixes or not os.path.exists(path):
+        return None, None
     digest, rows = None, {}
     with open(path) as fh:
         for line in fh:
@@ -118,9 +123,10 @@ def committed_traffic(wname, stage, w):
                 digest = parts[1]
             elif len(parts) >= 2 and parts[0] == "bytes_per_launch":
                 rows[" ".join(parts[2:])] = float(parts[1])
-    if digest != source_digest():
-        return None
-    return rows.get(name)
+    hits = [k for k in rows if k.startswith(prefixes)]
+    if len(hits) != 1:
+        return None, None
+    return hits[0], (rows[hits[0]] if digest == source_digest() else None)
 
 
 def calibration_copy():
@@ -136,22 +142,6 @@ def calibration_copy():
     torch.neg(src, out=dst)
     torch.cuda.synchronize()
     del src, dst, evict
-
-
-def _kernel_name(stage, w):
-    """Device kernel behind a timed stage in mixed precision on workload w
-    (the transform kernels are compiled for the padded lengths of the
-    configured grids; the theta pass of 1536-point lines runs the
-    runtime-length, workgroup-scope kernel)."""
-    nt = 3 * w["M_theta"]
-    nz = 3 * ((w["M_z"] - 1) // 2 + 1)
-    if stage == "theta":
-        return (f"nsc::k_theta<float, true, {nt}>" if nt in (48, 96, 192, 768)
-                else "nsc::k_theta<float, false, 0>")
-    if stage in ("zinv", "zfwd"):
-        ln = nz if nz in (48, 96, 192, 768, 1536) else 0
-        return f"nsc::k_{stage}<float, {ln}>"
-    return DEVICE_KERNEL.get(stage)
 
 
 def measure(wname, steps, warmup, precisions=("fp64", "mixed"), profile_steps=50):
@@ -255,10 +245,11 @@ def measure(wname, steps, warmup, precisions=("fp64", "mixed"), profile_steps=50
         best = max((k for k in kern if k not in ("factor",)),
                    key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
         kb = kern[best]
-        res["roofline"] = {"bound": "hbm", "kernel": best, "device_kernel": _kernel_name(best, w),
+        dev, traffic = committed_traffic(wname, best)
+        res["roofline"] = {"bound": "hbm", "kernel": best,
+                           "device_kernel": dev or " or ".join(STAGE_KERNELS.get(best, ())),
                            "achieved": kb["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": kb["frac"],
-                           "traffic": committed_traffic(wname, best, w),
+                           "frac": kb["frac"], "traffic": traffic,
                            "bytes_per_launch": kb["bytes_per_launch"],
                            "avg_launch_us": kb["avg_us"]}
         res["kernels"] = kern
@@ -492,7 +483,10 @@ def traffic_report(wname, fetch_csv, write_csv):
     and written)."""
     f = _pmc_means([fetch_csv])
     w = _pmc_means([write_csv])
-    cal = max((k for k in f if not k.startswith("nsc::")), key=lambda k: f[k]["FETCH_SIZE"])
+    cal = [k for k in f if "neg_kernel" in k and k in w]
+    if len(cal) != 1:
+        raise SystemExit(f"traffic report: expected one calibration kernel, found {cal}")
+    cal = cal[0]
     kib = 256 * 1024
     ff = kib / f[cal]["FETCH_SIZE"]
     fw = kib / w[cal]["WRITE_SIZE"]
