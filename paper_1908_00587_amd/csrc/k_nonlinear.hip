@@ -942,9 +942,15 @@ int block_for(const FftPlan &p, int nlines, int floor_threads) {
 int z_lines(const nsc_ctx *c, size_t esize) {
   const size_t budget = (size_t)c->lds_max - (size_t)c->d.nz * 16;  // twiddle entries
   int tm = (int)(budget / ((size_t)line_len(c->d.nz, esize) * esize));
-  // lines beyond one butterfly per thread are transformed in groups; the
-  // width of the transposed accesses (tm consecutive theta modes) matters more
-  if (tm > 16) tm = 16;
+  // at most 8 lines, a power of two: the transposed accesses (tm consecutive
+  // theta modes of each z row) then stay within aligned 64- or 128-byte
+  // segments, and smaller tiles let more workgroups share a compute unit
+  // (11-line tiles of the 1536-point FP32 lines, 88-byte segments across
+  // cache-line boundaries, took 29 % longer in the z-inverse pass; 16-line
+  // tiles of 768-point lines, one workgroup per CU, 3 % and 11 % longer in
+  // the FP32 z passes)
+  if (tm > 8) tm = 8;
+  if (tm > 1) tm = 1 << (31 - __builtin_clz((unsigned)tm));
   if (tm > c->d.mt) tm = c->d.mt;
   if (tm < 1) tm = 1;
   return tm;
