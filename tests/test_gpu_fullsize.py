@@ -39,6 +39,23 @@ def rel(a, b):
     return float((a - b).abs().max() / b.abs().max())
 
 
+def report(got, ref, p, tag):
+    """Print and return the error of each output field of a nonlinear term,
+    relative to the field and, over the modes other than (0,0) (the mean-flow
+    products dominate max|N|), relative to N there."""
+    names = ["N_r", "N_theta", "N_z", "N_T"][: got.shape[0]]
+    fl = torch.ones(p.M_theta, p.M_z, dtype=torch.bool)
+    fl[0, p.K] = False
+    worst = 0.0
+    for f, nm in enumerate(names):
+        d = (got[f] - ref[f]).abs()
+        e_all = float(d.max() / ref[f].abs().max())
+        e_fl = float(d[:, fl].max() / ref[f][:, fl].abs().max())
+        worst = max(worst, e_fl)
+        _say(f"  {tag} {nm}: rel {e_all:.2e}, over the fluctuating modes {e_fl:.2e}")
+    return worst
+
+
 ROWS = {"tc-heated-n64": [0, 1, 9, 31, 54, 62, 63], "tc-turb-n128": [0, 5, 64, 127]}
 
 
@@ -56,6 +73,10 @@ def test_nonlinear_full_size_sampled_rows(name, prec, tol):
     torch.cuda.synchronize()
     got = out.cpu()[:, rows]
     assert rel(got, ref) < tol
+    # per field: in mixed precision N_theta and N_T are small beside the
+    # products that make them up, so their own relative error is larger
+    # (measured up to 2e-5 on the counter-rotating grid); a sanity bound
+    assert report(got, ref, p, f"{name} {prec}") < (tol if prec == "fp64" else 1e-4)
     # the bound over all rows is at most the bound over the sampled rows (up
     # to the rounding of the transformed velocities: FP32 in mixed precision)
     c = float(c.cpu()[0])
@@ -160,6 +181,7 @@ def test_conv_full_size_sampled():
     err = rel(got, ref)
     _say("  mixed nonlinear rel err", err)
     assert err < 1e-5
+    assert report(got, ref, p, f"{CONV} mixed") < 1e-4
     assert 0.0 < c <= dt_rows * (1 + 1e-6)
     ctx.set_precision("fp64")
     with pytest.raises(nsc.NscError):
