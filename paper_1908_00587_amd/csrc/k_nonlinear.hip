@@ -429,23 +429,36 @@ k_theta_fx(Dims d, Grid g, const C2<T> *__restrict__ Z, C2<T> *__restrict__ W,
   // packing + pruned radix-3 stage (inverse: w = e^{+2 pi i/3}); butterfly
   // (p, q): a = Z_q, c = Z_{N-(M-q)} (zero for q = 0: mode M is not kept)
   constexpr double H3 = 0.86602540378443864676372317075294;  // sqrt(3)/2
+  // all loads of the thread's items first (kept ahead of the butterflies by
+  // a scheduling barrier), so that they are in flight together; q = 0 reads
+  // its own mode in place of the mirror and drops it
+  constexpr int NIT = (NP * MT + G - 1) / G;
+  C2<T> F1[NIT], F2[NIT], G1[NIT], G2[NIT];
 #pragma unroll
-  for (int it0 = 0; it0 < NP * MT; it0 += G) {
-    const int it = it0 + tid;
+  for (int i = 0; i < NIT; ++i) {
+    const int it = i * G + tid;
+    const int p = (it < NP * MT ? it : 0) / MT, q = (it < NP * MT ? it : 0) - p * MT;
+    const int qm = q == 0 ? 0 : MT - q;
+    const C2<T> *f1 = zl + (size_t)(2 * p) * fstride;
+    const bool two = 2 * p + 1 < NI;
+    F1[i] = f1[q];
+    G1[i] = f1[qm];
+    F2[i] = two ? f1[fstride + q] : C2<T>{T(0), T(0)};
+    G2[i] = two ? f1[fstride + qm] : C2<T>{T(0), T(0)};
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < NIT; ++i) {
+    const int it = i * G + tid;
     if (it < NP * MT) {
       const int p = it / MT, q = it - p * MT;
-      const C2<T> *f1 = zl + (size_t)(2 * p) * fstride;
-      const bool two = 2 * p + 1 < NI;
-      const C2<T> F1 = f1[q];
-      const C2<T> F2 = two ? f1[fstride + q] : C2<T>{T(0), T(0)};
-      C2<T> a, c{T(0), T(0)};
+      C2<T> a, c;
       if (q == 0) {
-        a = {F1.x, F2.x};
+        a = {F1[i].x, F2[i].x};
+        c = {T(0), T(0)};
       } else {
-        a = {F1.x - F2.y, F1.y + F2.x};
-        const C2<T> G1 = f1[MT - q];
-        const C2<T> G2 = two ? f1[fstride + MT - q] : C2<T>{T(0), T(0)};
-        c = {G1.x + G2.y, G2.x - G1.y};
+        a = {F1[i].x - F2[i].y, F1[i].y + F2[i].x};
+        c = {G1[i].x + G2[i].y, G2[i].x - G1[i].y};
       }
       // y0 = a + c, y1 = a + e^{4 pi i/3} c, y2 = a + e^{2 pi i/3} c
       const C2<T> t = {a.x - T(0.5) * c.x, a.y - T(0.5) * c.y};
