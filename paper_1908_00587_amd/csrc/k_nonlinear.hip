@@ -133,6 +133,7 @@ __device__ void mean_row(const Dims &d, const Grid &g, const double2 *__restrict
   mean[6 * n + j] = dt;
 }
 
+constexpr int ZU = 4;  // z-inverse items per round of loads (2: about half the gain)
 template <typename T, int NF, bool PIPE = false>
 __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz, const double2 *__restrict__ u,
                        C2<T> *__restrict__ Z, const TwT<T> *__restrict__ tw, int tm, int drop_mean,
@@ -155,12 +156,27 @@ __global__ void __launch_bounds__(kFftThreads) k_zinv(Dims d, Grid g, FftPlan pz
   // modes of each butterfly straight into it measured slower on the
   // 1536-point lines and no faster on the 192-point ones.)
   const int mz = d.mz;
-  for (Walk2 w(threadIdx.x, blockDim.x, mz); w.r < nl; w.next()) {
-    const int li = w.r;
-    const int kk = w.c;
-    const int k = kk - K;
-    const double2 v = derived<PIPE>(d, g, u, f, j, mt0 + li, kk, drop_mean != 0);
-    buf[li * ls + PD<T>((k >= 0 ? k : nz + k))] = {T(v.x), T(v.y)};
+  // ZU items per round, their loads issued together (items past the tile
+  // repeat its last line and are not stored)
+  Walk2 w(threadIdx.x, blockDim.x, mz);
+  while (w.r < nl) {
+    int li[ZU], kk[ZU];
+#pragma unroll
+    for (int i = 0; i < ZU; ++i) {
+      li[i] = w.r;
+      kk[i] = w.c;
+      w.next();
+    }
+    double2 v[ZU];
+#pragma unroll
+    for (int i = 0; i < ZU; ++i)
+      v[i] = derived<PIPE>(d, g, u, f, j, mt0 + (li[i] < nl ? li[i] : nl - 1), kk[i],
+                           drop_mean != 0);
+#pragma unroll
+    for (int i = 0; i < ZU; ++i) {
+      const int k = kk[i] - K;
+      if (li[i] < nl) buf[li[i] * ls + PD<T>((k >= 0 ? k : nz + k))] = {T(v[i].x), T(v[i].y)};
+    }
   }
   const int npad = nz - mz;
   for (Walk2 w(threadIdx.x, blockDim.x, npad); w.r < nl; w.next())
