@@ -579,7 +579,7 @@ k_sweep(Dims d, SweepArgs a) {
   const SweepSys &S = a.s[sys];
   const size_t P = d.nmodes;
   const int n = NR > 0 ? NR : d.nr;
-  constexpr int kUnrollCol = NR > 0 ? NR : 8;   // column copies
+  constexpr int kUnrollCol = NR > 0 ? NR : 8;   // column copy
   constexpr int kUnrollRows = NR > 0 ? NR : 1;  // row groups of the sweeps
   constexpr int kPf = NR > 0 ? kPfUnrolled : kPfRuntime;
   const int kp1 = d.kmax + 1;
@@ -607,14 +607,15 @@ k_sweep(Dims d, SweepArgs a) {
   const double *__restrict__ vals = F.vals + op;
   const double *__restrict__ edge = F.edge + op;
   auto C = [&](int j) -> Cd & { return col[j * kSweepLanes + lane]; };
-  // right side into the LDS column with all loads in flight together
-#pragma unroll kUnrollCol
-  for (int j = 0; j < n; ++j) C(j) = ld(b + (size_t)j * P);
   // Everything a row needs is requested well before the row: the factor
-  // rows kPf ahead (registers), the column entries kPc ahead (LDS reads),
-  // and the edge rows of both ends at the start.  One wavefront per
-  // workgroup: registers are plentiful, and the distance of these requests
-  // is what hides the memory latency of the recurrences.
+  // rows and the right side kPf rows ahead (registers), the column entries
+  // kPc ahead (LDS reads), and the edge rows of both ends at the start.  The
+  // right side enters with the factor rows rather than in a bulk copy before
+  // the sweeps.  (The solution leaves in one copy at the end: stored row by
+  // row during the back substitution, its stores fall under the same wait
+  // counter as the prefetched loads and slowed the velocity sweeps.)  One
+  // wavefront per workgroup: registers are plentiful, and the distance of
+  // these requests is what hides the memory latency of the recurrences.
   const int nm = n - 4;
   // Fully unrolled sweeps read the factor rows as raw buffer loads: the
   // lane's operator offset in one 32-bit register, the row and slot offset
@@ -657,16 +658,19 @@ k_sweep(Dims d, SweepArgs a) {
   const int tail_at = NR > 0 && nm - kPf > 0 ? nm - kPf : 0;          // forward row
   const int head_at = NR > 0 && 4 + kPf < n - 1 ? 4 + kPf : n - 1;    // backward row
   if (tail_at == 0) load_tail();
+  // right sides of the last four rows (after the ring's reach)
+  Cd rt[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) rt[r] = ld(b + (size_t)(nm + r) * P);
   double fa[kPf][4];
+  Cd rb[kPf];
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
     const int jj = r < nm ? r : nm - 1;
 #pragma unroll
     for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
+    rb[r] = ld(b + (size_t)jj * P);
   }
-  Cd cb[kPc];
-#pragma unroll
-  for (int r = 0; r < kPc; ++r) cb[r] = C(r < nm ? r : nm - 1);
   Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
 #pragma unroll kUnrollRows
   for (int j0 = 0; j0 < nm; j0 += kPf) {
@@ -677,7 +681,7 @@ k_sweep(Dims d, SweepArgs a) {
       if (j < nm) {
         // oldest terms first: the newest value y1 enters last, so the
         // row-to-row dependency is a single fused multiply-add
-        Cd y = cb[r % kPc];  // = C(j): j0 is a multiple of kPf, kPc divides kPf
+        Cd y = rb[r];  // right side of row j (j0 is a multiple of kPf)
         y = y - fa[r][0] * y4;
         y = y - fa[r][1] * y3;
         y = y - fa[r][2] * y2;
@@ -687,13 +691,11 @@ k_sweep(Dims d, SweepArgs a) {
         y2 = y1;
         y1 = y;
         C(j) = y;
-        // row j + kPc has not been written yet (rows are written in order)
-        const int jc = j + kPc < nm ? j + kPc : nm - 1;
-        cb[r % kPc] = C(jc);
       }
       const int jn = j + kPf < nm ? j + kPf : nm - 1;
 #pragma unroll
       for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
+      rb[r] = ld(b + (size_t)jn * P);
       // keep the source order: the loads of row jn go out now, not next to
       // their use kPf rows later
       if constexpr (NR > 0) __builtin_amdgcn_sched_barrier(0);
@@ -702,7 +704,7 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int j = nm + r;
-    Cd y = C(j);
+    Cd y = rt[r];
 #pragma unroll
     for (int t = 1; t <= 4; ++t) y = y - lt[r][4 - t] * C(j - t);
     const int tt = n - 1 - j;
@@ -720,6 +722,7 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
     for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
   }
+  Cd cb[kPc];
 #pragma unroll
   for (int r = 0; r < kPc; ++r) cb[r] = C(n - 1 - r >= 4 ? n - 1 - r : 4);
   Cd x1{0, 0}, x2{0, 0}, x3{0, 0}, x4{0, 0};
