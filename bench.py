@@ -573,6 +573,8 @@ def main():
                     help="time the main workload only")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--adjoint-ckpt", type=int, default=20)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the adjoint/forward ratio on the adjoint workload's schedule")
     ap.add_argument("--adjoint-largest", action="store_true",
                     help="print the adjoint/forward ratio on the largest workload's schedule "
                          "(about two minutes) instead of the time step")
@@ -588,6 +590,9 @@ def main():
         return
     if args.adjoint_largest:
         print(json.dumps(run_adjoint_largest()), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps(run_adjoint(args.adjoint_steps, ckpt=args.adjoint_ckpt)), flush=True)
         return
     from paper_1908_00587_amd.workloads import WORKLOADS
     w = WORKLOADS[args.workload]
