@@ -1712,8 +1712,10 @@ __global__ void k_adj_f(Dims d, Grid g, const double2 *__restrict__ sf, const do
 // Input adjoints: Xbar^n = fbar/dt + (1-c) L^T fbar; Nbar^q = c fbar,
 // Nbar^n = (1-c) fbar; back to (r, theta, z, T) and accumulated.
 __global__ void __launch_bounds__(256)
-k_adj_in(Dims d, Grid g, const double2 *__restrict__ fb, double idt, double cc,
-         double2 *__restrict__ ubn, double2 *__restrict__ nbn, double2 *__restrict__ nbq) {
+k_adj_in(Dims d, Grid g, const int *__restrict__ trow, const int *__restrict__ tcnt,
+         const double *__restrict__ twt, const double2 *__restrict__ fb, double idt, double cc,
+         double2 *__restrict__ ubn, double2 *__restrict__ nbn, double2 *__restrict__ nbq,
+         int overwrite) {
   const int md = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (md >= d.nmodes) return;
@@ -1735,37 +1737,45 @@ k_adj_in(Dims d, Grid g, const double2 *__restrict__ fb, double idt, double cc,
     const double2 *f = fb + (size_t)c * n * P + md;
     const double q = c == 0 ? (double)(m + 1) : (c == 1 ? (double)(m >= 1 ? m - 1 : 1 - m) : (double)m);
     const Cd v = ld(f + (size_t)j * P);
-    const Cd LT = wt_rowc(g, g.d2, n, j, f, P, false) + wt_rowc(g, g.d1, n, j, f, P, true) -
-                  (q * q * r2 + k2) * v;
+    // (D2 + D1/r)^T f at row j from the column's table (uniform per workgroup)
+    Cd lt = {0, 0};
+    const int cnt = tcnt[j];
+    for (int e = 0; e < cnt; ++e)
+      lt = fmac(twt[j * kTrans + e], ld(f + (size_t)trow[j * kTrans + e] * P), lt);
+    const Cd LT = lt - (q * q * r2 + k2) * v;
     const double sc = c == 3 ? ce / d.pr : ce;
     xb[c] = idt * v + sc * LT;
     fv[c] = v;
   }
-  auto acc = [&](double2 *base, int f, Cd v) {
+  auto acc = [&](double2 *base, int f, Cd v, int bit) {
     double2 *p = base + ((size_t)f * n + j) * P + md;
-    p->x += v.x;
-    p->y += v.y;
+    if (overwrite & bit) {
+      *p = make_double2(v.x, v.y);
+    } else {
+      p->x += v.x;
+      p->y += v.y;
+    }
   };
   // X+- = X_r +- i X_theta  =>  Xbar_r = Xbar+ + Xbar-, Xbar_theta = -i (Xbar+ - Xbar-)
   const Cd ur = xb[0] + xb[1];
   const Cd dd = xb[0] - xb[1];
   const Cd ut = {dd.y, -dd.x};
-  acc(ubn, 0, ur);
-  acc(ubn, 1, ut);
-  acc(ubn, 2, xb[2]);
-  if (d.heated) acc(ubn, 3, xb[3]);
+  acc(ubn, 0, ur, 1);
+  acc(ubn, 1, ut, 1);
+  acc(ubn, 2, xb[2], 1);
+  if (d.heated) acc(ubn, 3, xb[3], 1);
   const Cd fr = fv[0] + fv[1];
   const Cd fdd = fv[0] - fv[1];
   const Cd ft = {fdd.y, -fdd.x};
-  acc(nbq, 0, cc * fr);
-  acc(nbq, 1, cc * ft);
-  acc(nbq, 2, cc * fv[2]);
-  acc(nbn, 0, ce * fr);
-  acc(nbn, 1, ce * ft);
-  acc(nbn, 2, ce * fv[2]);
+  acc(nbq, 0, cc * fr, 4);
+  acc(nbq, 1, cc * ft, 4);
+  acc(nbq, 2, cc * fv[2], 4);
+  acc(nbn, 0, ce * fr, 2);
+  acc(nbn, 1, ce * ft, 2);
+  acc(nbn, 2, ce * fv[2], 2);
   if (d.heated) {
-    acc(nbq, 3, cc * fv[3]);
-    acc(nbn, 3, ce * fv[3]);
+    acc(nbq, 3, cc * fv[3], 4);
+    acc(nbn, 3, ce * fv[3], 2);
   }
 }
 
@@ -1903,7 +1913,8 @@ hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *o
 }
 
 hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ubar_n,
-                            double *nbar_n, double *nbar_q, double dt, double cc) {
+                            double *nbar_n, double *nbar_q, double dt, double cc,
+                            int overwrite) {
   const double2 *ub = reinterpret_cast<const double2 *>(ubar_out);
   double2 *sx = reinterpret_cast<double2 *>(c->s_x);
   double2 *sf = reinterpret_cast<double2 *>(c->s_f);
@@ -1937,9 +1948,10 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
   else
     hipLaunchKernelGGL(k_adj_poisson, mode_grid(c, 1), dim3(256), 0, c->stream, c->d, c->fp, sp, sg);
   hipLaunchKernelGGL(k_adj_f, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sg, sx);
-  hipLaunchKernelGGL(k_adj_in, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sx, 1.0 / dt,
-                     cc, reinterpret_cast<double2 *>(ubar_n), reinterpret_cast<double2 *>(nbar_n),
-                     reinterpret_cast<double2 *>(nbar_q));
+  hipLaunchKernelGGL(k_adj_in, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g,
+                     c->t_row, c->t_cnt, c->t_wt, sx, 1.0 / dt, cc,
+                     reinterpret_cast<double2 *>(ubar_n), reinterpret_cast<double2 *>(nbar_n),
+                     reinterpret_cast<double2 *>(nbar_q), overwrite);
   return hipGetLastError();
 }
 

@@ -292,21 +292,19 @@ int nsc::step_vjp_impl(nsc_ctx *c, const double *u, const double *stages,
   const int nc = c->n_corr;
   double *abar = work, *bbar = abar + fld, *xa = bbar + fld, *xb = xa + fld;
   TRY(ensure_factors(c, c->dt, c->c));
-  HIPCHK(launch_fill_zero(c, ubar, fld));
-  HIPCHK(launch_fill_zero(c, work, 4 * fld));  // abar, bbar and both x buffers
+  // the first solve VJP writes ubar and abar, every one writes bbar; only
+  // the nonlinear VJP's output starts from zero
   const double *xbar = ubar_next;
   for (int q = nc; q >= 1; --q) {
     // X^(q+1) = S(u, a, N(X^(q)))
-    if (q != nc) HIPCHK(launch_fill_zero(c, bbar, fld));
-    HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+    HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c, q == nc ? 7 : 4));
     double *xn = (xbar == xa) ? xb : xa;
-    if (q != nc) HIPCHK(launch_fill_zero(c, xn, fld));
+    HIPCHK(launch_fill_zero(c, xn, fld));
     HIPCHK(launch_nonlinear_vjp(c, c->precision, stages + (size_t)(q - 1) * fld, bbar, xn));
     xbar = xn;
   }
   // X^(1) = S(u, a, a)
-  HIPCHK(launch_fill_zero(c, bbar, fld));
-  HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c));
+  HIPCHK(launch_solve_vjp(c, xbar, ubar, abar, bbar, c->dt, c->c, nc >= 1 ? 4 : 7));
   HIPCHK(launch_add(c, abar, bbar, fld));
   HIPCHK(launch_nonlinear_vjp(c, c->precision, u, abar, ubar));
   return NSC_OK;
@@ -335,7 +333,8 @@ int nsc_destroy(nsc_ctx *c) {
   if (!c) return NSC_OK;
   void *ptrs[] = {c->tables, c->tw64_t, c->tw64_z, c->tw32_t, c->tw32_z, c->zbuf, c->wbuf,
                   c->cfl_part, c->cfl_val, c->e_part, c->s_f, c->s_g, c->s_p, c->s_x,
-                  c->s_lam, c->s_vjp, c->s_u1, c->s_nn, c->s_nq, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv};
+                  c->s_lam, c->s_vjp, c->s_u1, c->s_nn, c->s_nq, c->s_adj, c->s_mean, c->inf.resp, c->inf.ainv,
+                  c->t_row, c->t_cnt, c->t_wt};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   free_factors(&c->fv);
@@ -508,6 +507,27 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   HIPCHK(hipMemcpy(p_lw, lw.data(), np * nw * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p_s, s.data(), n * sizeof(int), hipMemcpyHostToDevice));
   c->g = Grid{p_r, p_rinv, p_d1, p_d2, p_s, p_dr, p_cc, p_lw, pipe ? nw : 0};
+  // the adjoint's transposed rows of D2 + D1/r: column j collects the rows
+  // whose windows hold it (nine inside, up to thirteen where the one-sided
+  // wall windows overlap)
+  {
+    std::vector<int> trow((size_t)n * kTrans, 0), tcnt(n, 0);
+    std::vector<double> twt((size_t)n * kTrans, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < kStencil; ++t) {
+        const int j = s[i] + t;
+        if (tcnt[j] >= kTrans) return NSC_ERR_ARG;
+        trow[(size_t)j * kTrans + tcnt[j]] = i;
+        twt[(size_t)j * kTrans + tcnt[j]] = lw[(size_t)i * kStencil + t];
+        ++tcnt[j];
+      }
+    TRY(dmalloc((void **)&c->t_row, trow.size() * sizeof(int)));
+    TRY(dmalloc((void **)&c->t_cnt, tcnt.size() * sizeof(int)));
+    TRY(dmalloc((void **)&c->t_wt, twt.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(c->t_row, trow.data(), trow.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->t_cnt, tcnt.data(), tcnt.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->t_wt, twt.data(), twt.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
 
   // twiddles
   {

@@ -13,6 +13,7 @@ namespace nsc {
 constexpr int kStencil = 9;    // nine-point radial stencils (section 2.1 default)
 constexpr int kHalf = 4;       // stencil half width
 constexpr int kSlots = 9;      // compact LU row: L[4] | 1/U_jj | U[4]
+constexpr int kTrans = 16;     // slots per column of a transposed stencil (13 used at most)
 constexpr int kEdge = 20;      // extra U entries of rows 0..3 + extra L of rows N-4..N-1
 constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 12;
@@ -117,6 +118,10 @@ struct nsc_ctx {
   double *s_p = nullptr;    // [N_r][modes] complex p0
   double *s_x = nullptr;    // [4][N_r][modes] complex X0+, X0-, X0z, T
   double *s_lam = nullptr;  // [modes][2] complex
+  // transposed rows of D2 + D1/r (cylinders): column j's entries (row,
+  // weight), kTrans slots per column, t_cnt[j] of them used
+  int *t_row = nullptr, *t_cnt = nullptr;
+  double *t_wt = nullptr;
   double *s_vjp = nullptr;  // adjoint workspaces of nsc_step_vjp: 4 states (allocated on first use)
   double *s_u1 = nullptr;   // [F][N_r][modes] complex intermediate state
   double *s_nn = nullptr;   // [F][N_r][modes] complex N^n
@@ -189,8 +194,10 @@ hipError_t launch_finalize(const nsc_ctx *c, double *out, double *p_out);
 hipError_t launch_energy(const nsc_ctx *c, const double *u, double *e_dev);
 hipError_t launch_seed(const nsc_ctx *c, const double *amps, double *out_pert);
 hipError_t launch_add_base(const nsc_ctx *c, const double *pert_tilde, double *out);
+// overwrite: bit 1 ubar_n, 2 nbar_n, 4 nbar_q written instead of accumulated
 hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ubar_n,
-                            double *nbar_n, double *nbar_q, double dt, double cc);
+                            double *nbar_n, double *nbar_q, double dt, double cc,
+                            int overwrite = 0);
 hipError_t launch_energy_grad(const nsc_ctx *c, const double *u, double *gout);
 hipError_t launch_nonlinear_vjp(const nsc_ctx *c, int prec, const double *u, const double *nbar,
                                 double *ubar);
