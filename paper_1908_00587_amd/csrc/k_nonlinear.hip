@@ -701,7 +701,8 @@ __global__ void __launch_bounds__(kFftThreads) k_zfwd(Dims d, Grid g, FftPlan pz
   const C2<T> *in = W + ((size_t)f * d.nr + j) * nz * d.mt;
   // FP32: ZU items per round, their loads issued together (items past the
   // last z row repeat it and are not stored; 768-point lines 454 -> 347 us,
-  // 1536-point 6.5 -> 5.8 ms).  FP64, two percent slower so, one at a time.
+  // 1536-point 6.5 -> 5.8 ms).  FP64 keeps one item per round (four were
+  // two percent slower).
   constexpr int ZF = sizeof(T) == 4 ? ZU : 1;
   Walk2 w(threadIdx.x, blockDim.x, nl);
   while (w.r < nz) {
