@@ -93,15 +93,22 @@ STAGE_KERNELS = {"theta": ("nsc::k_theta<float,", "nsc::k_theta_fx<float,"),
 
 
 def source_digest():
-    """SHA-256 over the HIP/C++ sources of the library (sorted by name): the
-    traffic counters of a committed profile apply only to the same kernels."""
+    """SHA-256 over the library's HIP/C++ sources (sorted by name) with the
+    comments and the layout taken out: the traffic counters of a committed
+    profile apply only to the same code, and a change of wording in a
+    comment does not make them stale."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_1908_00587_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+            with open(os.path.join(csrc, name)) as fh:
+                text = fh.read()
+            # one left-to-right pass, so that a "/*" inside a line comment
+            # (or a "//" inside a block comment) is taken as comment text
+            text = re.sub(r"//[^\n]*|/\*.*?\*/", " ", text, flags=re.S)
+            h.update(name.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()
 
 
@@ -109,8 +116,8 @@ def committed_traffic(wname, stage):
     """(device kernel, HBM bytes per launch) of a stage from the committed
     counter summary profiles/hbm-traffic_<workload>.txt (FETCH_SIZE +
     WRITE_SIZE, each scaled by the calibration kernel's reading); bytes None
-    when the file is missing, the kernel sources changed since it was taken,
-    or no single kernel of the file matches the stage."""
+    when the file is missing, the library code changed since the counters
+    were taken, or no single kernel of the file matches the stage."""
     path = os.path.join(ROOT, "profiles", f"hbm-traffic_{wname}.txt")
     prefixes = STAGE_KERNELS.get(stage, ())
     if not prefixes or not os.path.exists(path):
@@ -119,7 +126,7 @@ def committed_traffic(wname, stage):
     with open(path) as fh:
         for line in fh:
             parts = line.split()
-            if len(parts) == 2 and parts[0] == "source_sha256":
+            if len(parts) == 2 and parts[0] == "code_sha256":
                 digest = parts[1]
             elif len(parts) >= 2 and parts[0] == "bytes_per_launch":
                 rows[" ".join(parts[2:])] = float(parts[1])
@@ -494,7 +501,7 @@ def traffic_report(wname, fetch_csv, write_csv):
            f"# calibration kernel {cal}: FETCH_SIZE {f[cal]['FETCH_SIZE']:.1f} KiB, "
            f"WRITE_SIZE {w[cal]['WRITE_SIZE']:.1f} KiB for {kib} KiB each "
            f"-> factors {ff:.4f} (fetch), {fw:.4f} (write)",
-           f"source_sha256 {source_digest()}"]
+           f"code_sha256 {source_digest()}"]
     for k in sorted(f):
         if k.startswith("nsc::") and k in w:
             b = 1024 * (ff * f[k]["FETCH_SIZE"] + fw * w[k]["WRITE_SIZE"])

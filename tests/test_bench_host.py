@@ -1,8 +1,8 @@
 """Host logic of bench.py (no GPU): the HBM traffic summary scales each
 counter by what it reads for the 256 MiB calibration copy, and the
 roofline's traffic field finds each stage's kernel in the committed
-summaries by name, and only while the kernel sources are the ones the
-counters were taken from."""
+summaries by name, and only while the library code is the code the
+counters were taken from (comments aside)."""
 import csv
 import importlib.util
 import os
@@ -59,7 +59,7 @@ def test_traffic_report_scales_by_the_calibration_copy(bench, tmp_path):
     rows = {ln.split()[2]: float(ln.split()[1]) for ln in text.splitlines()
             if ln.startswith("bytes_per_launch")}
     assert rows == {"nsc::k_demo<float>": pytest.approx(4 * 1024 * 1024, rel=1e-12)}
-    assert "source_sha256 " + bench.source_digest() in text
+    assert "code_sha256 " + bench.source_digest() in text
 
 
 @pytest.mark.parametrize("name", WORKLOADS)
@@ -79,10 +79,23 @@ def test_committed_traffic_names_one_kernel_per_stage(bench, name):
             assert "<float," in dev
 
 
-def test_committed_traffic_only_for_the_same_sources(bench, monkeypatch):
+def test_committed_traffic_only_for_the_same_code(bench, monkeypatch):
     dev, b = bench.committed_traffic("tc-heated-n64", "theta")
     if b is None:
-        pytest.skip("the committed summary belongs to other kernel sources")
+        pytest.skip("the committed summary belongs to other library code")
     monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)
     dev2, b2 = bench.committed_traffic("tc-heated-n64", "theta")
     assert dev2 == dev and b2 is None
+
+
+def test_code_digest_ignores_comments_only(bench, tmp_path, monkeypatch):
+    """The digest sees code, not comments or layout."""
+    src = tmp_path / "paper_1908_00587_amd" / "csrc"
+    src.mkdir(parents=True)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (src / "a.hip").write_text("int f(int x) {  // twice\n  return 2 * x; /* doubled */ }\n")
+    d0 = bench.source_digest()
+    (src / "a.hip").write_text("int f(int x) {  // two times x\n\n  return 2 * x;\n}\n")
+    assert bench.source_digest() == d0
+    (src / "a.hip").write_text("int f(int x) { return 3 * x; }\n")
+    assert bench.source_digest() != d0
