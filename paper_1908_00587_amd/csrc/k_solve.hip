@@ -173,14 +173,27 @@ k_factor(Dims d, Grid g, Factors F0, Factors F1, int kind, double alpha, double 
     else
       eliminate(std::integral_constant<int, 8>{}, rk, dinv);
     // row k is final
-    double *v = F.vals + (size_t)k * kSlots * nops + op;
+    double lo[4], up[4];
     for (int t = 1; t <= 4; ++t) {
       const int c = k - t;
-      v[(size_t)(4 - t) * nops] = c >= 0 ? W(rk, c - k + 8) : 0.0;
+      lo[4 - t] = c >= 0 ? W(rk, c - k + 8) : 0.0;
       const int cu = k + t;
-      v[(size_t)(4 + t) * nops] = cu < n ? W(rk, cu - k + 8) : 0.0;
+      up[t - 1] = cu < n ? W(rk, cu - k + 8) : 0.0;
+    }
+    double *v = F.vals + (size_t)k * kSlots * nops + op;
+    for (int t = 0; t < 4; ++t) {
+      v[(size_t)t * nops] = lo[t];
+      v[(size_t)(5 + t) * nops] = up[t];
     }
     v[(size_t)4 * nops] = dinv;
+    if (F.pk) {
+      double *pl = F.pk + ((size_t)k * 2 * nops + op) * 4;
+      double *pu = pl + (size_t)nops * 4;
+      for (int t = 0; t < 4; ++t) {
+        pl[t] = lo[t];
+        pu[t] = up[t];
+      }
+    }
     if (k <= 3)
       for (int c = k + 5; c <= 8 && c < n; ++c)
         F.edge[(size_t)(edge_off(k) + c - (k + 5)) * nops + op] = W(rk, c - k + 8);
@@ -546,9 +559,9 @@ struct SweepArgs {
 };
 constexpr int kSweepLanes = 64;
 
-// factor rows in flight per sweep: fully unrolled 64-row sweeps (issued in
-// that order by scheduling barriers; 8 to 16 rows measure the same), and
-// runtime row counts
+// factor rows in flight per sweep: fully unrolled sweeps (issued in that
+// order by scheduling barriers; 16 or 20 rows measure the same), and runtime
+// row counts
 constexpr int kPfUnrolled = 12;
 constexpr int kPfRuntime = 16;
 constexpr int kPc = 4;  // column entries read ahead per sweep (divides the ring depths)
@@ -634,23 +647,43 @@ k_sweep(Dims d, SweepArgs a) {
     else
       return vals[((size_t)j * kSlots + sl) * nops];
   };
+  // The four L entries (part 0) or the four off-diagonal U entries (part 1)
+  // of row j into o[0..3].  Unrolled: two 16-byte loads from the row-packed
+  // copy, so that a row costs three memory instructions with its right side
+  // or its diagonal instead of five.
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+      F.pk, 0, (int)((size_t)n * 8 * nops * sizeof(double)), kBufferWord3);
+  const int poff = op * (int)(4 * sizeof(double));
+  auto quad = [&](int j, int part, double *o) {
+    if constexpr (NR > 0) {
+      const int so = (int)(((size_t)j * 2 + part) * nops * 4 * sizeof(double));
+      const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(prs, poff, so, 0));
+      const double2 c = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(prs, poff + 16, so, 0));
+      o[0] = a.x;
+      o[1] = a.y;
+      o[2] = c.x;
+      o[3] = c.y;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[t] = row(j, part ? 5 + t : t);
+    }
+  };
   // last four rows (forward) and first four rows (backward): band entries
   // and the extra envelope entries, requested kPf rows before their use so
   // that they do not hold registers through the bulk of the sweeps
   double lt[4][4], le[10], ut[4][5], ue[10];
   auto load_tail = [&] {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) lt[r][t] = row(nm + r, t);
+    for (int r = 0; r < 4; ++r) quad(nm + r, 0, lt[r]);
 #pragma unroll
     for (int e = 0; e < 10; ++e) le[e] = edge[(size_t)(10 + e) * nops];
   };
   auto load_head = [&] {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int t = 0; t < 5; ++t) ut[r][t] = row(r, 4 + t);
+    for (int r = 0; r < 4; ++r) {
+      ut[r][0] = row(r, 4);
+      quad(r, 1, ut[r] + 1);
+    }
 #pragma unroll
     for (int e = 0; e < 10; ++e) ue[e] = edge[(size_t)e * nops];
   };
@@ -667,8 +700,7 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
     const int jj = r < nm ? r : nm - 1;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) fa[r][t] = row(jj, t);
+    quad(jj, 0, fa[r]);
     rb[r] = ld(b + (size_t)jj * P);
   }
   Cd y1{0, 0}, y2{0, 0}, y3{0, 0}, y4{0, 0};
@@ -693,8 +725,7 @@ k_sweep(Dims d, SweepArgs a) {
         C(j) = y;
       }
       const int jn = j + kPf < nm ? j + kPf : nm - 1;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) fa[r][t] = row(jn, t);
+      quad(jn, 0, fa[r]);
       rb[r] = ld(b + (size_t)jn * P);
       // keep the source order: the loads of row jn go out now, not next to
       // their use kPf rows later
@@ -719,8 +750,8 @@ k_sweep(Dims d, SweepArgs a) {
 #pragma unroll
   for (int r = 0; r < kPf; ++r) {
     const int jj = n - 1 - r >= 4 ? n - 1 - r : 4;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) u[r][t] = row(jj, 4 + t);
+    u[r][0] = row(jj, 4);
+    quad(jj, 1, u[r] + 1);
   }
   Cd cb[kPc];
 #pragma unroll
@@ -750,8 +781,8 @@ k_sweep(Dims d, SweepArgs a) {
         cb[i] = C(jc);
       }
       const int jn = j - kPf >= 4 ? j - kPf : 4;
-#pragma unroll
-      for (int t = 0; t < 5; ++t) u[r][t] = row(jn, 4 + t);
+      u[r][0] = row(jn, 4);
+      quad(jn, 1, u[r] + 1);
       // keep the source order: the loads of row jn go out now, not next to
       // their use kPf rows later
       if constexpr (NR > 0) __builtin_amdgcn_sched_barrier(0);
@@ -2000,12 +2031,12 @@ hipError_t launch_solve_sweeps(const nsc_ctx *c, int stage, const double *nn, co
   auto launch = [&](const SweepArgs &a, int nsys, auto family) {
     constexpr int FAM = decltype(family)::value;
     dim3 gr((d.nmodes + kSweepLanes - 1) / kSweepLanes, nsys);
-    // the unrolled variant addresses its factors with 32-bit buffer offsets
-    const bool fits = (size_t)d.nr * kSlots * sizeof(double) *
-                          (size_t)(c->fv.nops > c->fp.nops ? c->fv.nops : c->fp.nops) <
-                      ((size_t)1 << 31);
-    if (lds && d.nr == 64 && fits)
+    // the unrolled variant reads the row-packed factors with 32-bit buffer
+    // offsets (allocated where sweeps_unrolled holds)
+    if (lds && c->fv.pk && d.nr == 64)
       hipLaunchKernelGGL((k_sweep<true, FAM, 64>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
+    else if (lds && c->fv.pk)
+      hipLaunchKernelGGL((k_sweep<true, FAM, 32>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
     else if (lds)
       hipLaunchKernelGGL((k_sweep<true, FAM, 0>), gr, dim3(kSweepLanes), shm, c->stream, d, a);
     else

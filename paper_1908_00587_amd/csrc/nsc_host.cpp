@@ -163,18 +163,20 @@ bool mul_ok(size_t a, size_t b, size_t *out) {
   return true;
 }
 
-int alloc_factors(Factors *f, int nq, int kp1, int nr) {
+int alloc_factors(Factors *f, int nq, int kp1, int nr, bool packed) {
   f->nq = nq;
   f->nops = nq * kp1;
   TRY(dmalloc((void **)&f->vals, (size_t)nr * kSlots * f->nops * sizeof(double)));
   TRY(dmalloc((void **)&f->edge, (size_t)kEdge * f->nops * sizeof(double)));
+  if (packed) TRY(dmalloc((void **)&f->pk, (size_t)nr * 8 * f->nops * sizeof(double)));
   return NSC_OK;
 }
 
 void free_factors(Factors *f) {
   if (f->vals) (void)hipFree(f->vals);
   if (f->edge) (void)hipFree(f->edge);
-  f->vals = f->edge = nullptr;
+  if (f->pk) (void)hipFree(f->pk);
+  f->vals = f->edge = f->pk = nullptr;
 }
 
 int ensure_factors(nsc_ctx *c, double dt, double cc) {
@@ -581,9 +583,10 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
 
   // factors
   const int kp1 = d.kmax + 1;
-  TRY(alloc_factors(&c->fv, d.mt + 1, kp1, n));
-  TRY(alloc_factors(&c->fp, d.mt, kp1, n));
-  if (d.heated) TRY(alloc_factors(&c->ft, d.mt, kp1, n));
+  const bool packed = sweeps_unrolled(d, (d.mt + 1) * kp1);
+  TRY(alloc_factors(&c->fv, d.mt + 1, kp1, n, packed));
+  TRY(alloc_factors(&c->fp, d.mt, kp1, n, packed));
+  if (d.heated) TRY(alloc_factors(&c->ft, d.mt, kp1, n, packed));
   c->inf.nops = d.mt * kp1;
   TRY(dmalloc((void **)&c->inf.resp, (size_t)8 * n * c->inf.nops * sizeof(double)));
   TRY(dmalloc((void **)&c->inf.ainv, (size_t)4 * c->inf.nops * sizeof(double)));

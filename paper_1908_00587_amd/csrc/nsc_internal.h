@@ -61,12 +61,24 @@ __host__ __device__ __forceinline__ int odd_off(const Grid &g, int q) { return (
 
 // Compact no-pivot LU factors of a family of radial operators.
 // vals: [N_r][kSlots][nops], edge: [kEdge][nops]; op = q * (K+1) + |k|.
+// pk (only where the fully unrolled sweeps run, else null): the same rows
+// packed per operator, [N_r][2][nops][4] = L slots 0-3, then U slots 5-8,
+// so that a lane fetches four entries of a row with two 16-byte loads.
 struct Factors {
   double *vals = nullptr;
   double *edge = nullptr;
+  double *pk = nullptr;
   int nq = 0;   // number of q values
   int nops = 0;
 };
+
+// The sweeps run fully unrolled (column in LDS, 32 or 64 radial points,
+// factor offsets within 32 bits) for these grids; nops_max is the largest
+// operator count of the context's factor families.  Their factors carry pk.
+inline bool sweeps_unrolled(const Dims &d, int nops_max) {
+  return (d.nr == 64 || d.nr == 32) &&
+         (size_t)d.nr * kSlots * sizeof(double) * (size_t)nops_max < ((size_t)1 << 31);
+}
 
 // Homogeneous (influence) responses per (m, |k|), op = m*(K+1)+|k|:
 // resp: [8][N_r][nops] = p1, p2, X+1, X+2, X-1, X-2, h1, h2 (X_z,j = -i kappa h_j)
