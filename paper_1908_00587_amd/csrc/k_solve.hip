@@ -187,12 +187,19 @@ k_factor(Dims d, Grid g, Factors F0, Factors F1, int kind, double alpha, double 
     }
     v[(size_t)4 * nops] = dinv;
     if (F.pk) {
-      double *pl = F.pk + ((size_t)k * 2 * nops + op) * 4;
-      double *pu = pl + (size_t)nops * 4;
+      auto at = [&](double *base, int row, int part) {
+        return base + (((size_t)row * 2 + part) * nops + op) * 4;
+      };
       for (int t = 0; t < 4; ++t) {
-        pl[t] = lo[t];
-        pu[t] = up[t];
+        at(F.pk, k, 0)[t] = lo[t];
+        at(F.pk, k, 1)[t] = up[t];
       }
+      // L(k, k - t) in column k - t, U(k, k + t) in column k + t
+      if (F.pc)
+        for (int t = 1; t <= 4; ++t) {
+          if (k - t >= 0) at(F.pc, k - t, 0)[t - 1] = lo[4 - t];
+          if (k + t < n) at(F.pc, k + t, 1)[t - 1] = up[t - 1];
+        }
     }
     if (k <= 3)
       for (int c = k + 5; c <= 8 && c < n; ++c)
@@ -1470,13 +1477,50 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
   const double *__restrict__ vals = F.vals + op;
   const double *__restrict__ edge = F.edge + op;
   auto V = [&](int row, int slot) { return vals[((size_t)row * kSlots + slot) * nops]; };
+  // Unrolled: raw buffer loads (operator offset in one 32-bit register, row
+  // offset in a scalar register) of the packed rows (part 0: L row, 1: U
+  // row) and columns (2: L below the diagonal, 3: U above it), two 16-byte
+  // loads per part; else the compact rows.
+  const size_t n8 = (size_t)n * nops * sizeof(double);
+  const __amdgpu_buffer_rsrc_t rv =
+      __builtin_amdgcn_make_buffer_rsrc(F.vals, 0, (int)(n8 * kSlots), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(F.pk, 0, (int)(n8 * 8), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(F.pc, 0, (int)(n8 * 8), kBufferWord3);
+  const int o8 = op * (int)sizeof(double);
+  auto dg = [&](int j) -> double {  // 1/U_jj
+    if constexpr (NR > 0)
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                            rv, o8, (j * kSlots + 4) * (int)nops * 8, 0));
+    else
+      return V(j, 4);
+  };
+  auto quad = [&](int j, int part, double *o) {
+    if constexpr (NR > 0) {
+      const int so = (j * 2 + (part & 1)) * (int)nops * 32;
+      const __amdgpu_buffer_rsrc_t r = part < 2 ? rk : rc;
+      const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, 4 * o8, so, 0));
+      const double2 b = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, 4 * o8 + 16, so, 0));
+      o[0] = a.x;
+      o[1] = a.y;
+      o[2] = b.x;
+      o[3] = b.y;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        o[t] = part == 0 ? V(j, t)
+             : part == 1 ? V(j, 5 + t)
+             : part == 2 ? V(j + t + 1, 3 - t)   // L(j + t + 1, j)
+                         : V(j - t - 1, 5 + t);  // U(j - t - 1, j)
+    }
+  };
   // U^T y = b: rows 0..8 with the top envelope entries
   {
     double hu[9][5], he[10];
 #pragma unroll
-    for (int j = 0; j < 9; ++j)
-#pragma unroll
-      for (int t = 0; t < 5; ++t) hu[j][t] = V(j, 4 + t);  // U(j, j + t), t = 0 the inverse diagonal
+    for (int j = 0; j < 9; ++j) {  // U(j, j + t), t = 0 the inverse diagonal
+      hu[j][0] = dg(j);
+      quad(j, 1, hu[j] + 1);
+    }
 #pragma unroll
     for (int e = 0; e < 10; ++e) he[e] = edge[(size_t)e * nops];
 #pragma unroll
@@ -1492,14 +1536,14 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
     }
   }
   {
-    // bulk rows 9..N-1: U(j-t, j) = slot 4 + t of row j - t, 1/U_jj = slot 4 of row j
+    // bulk rows 9..N-1: the U column above row j (U(j - t, j) at t) and
+    // 1/U_jj at 0
     double fa[kPfT][5];
 #pragma unroll
     for (int r = 0; r < kPfT; ++r) {
       const int j = 9 + r < n ? 9 + r : n - 1;
-#pragma unroll
-      for (int t = 1; t <= 4; ++t) fa[r][t] = V(j - t, 4 + t);
-      fa[r][0] = V(j, 4);
+      quad(j, 3, fa[r] + 1);
+      fa[r][0] = dg(j);
     }
     Cd y1 = C(8), y2 = C(7), y3 = C(6), y4 = C(5);
 #pragma unroll kUnrollRows
@@ -1521,19 +1565,16 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
           C(j) = y;
         }
         const int jn = j + kPfT < n ? j + kPfT : n - 1;
-#pragma unroll
-        for (int t = 1; t <= 4; ++t) fa[r][t] = V(jn - t, 4 + t);
-        fa[r][0] = V(jn, 4);
+        quad(jn, 3, fa[r] + 1);
+        fa[r][0] = dg(jn);
       }
     }
   }
   // L^T x = y: rows N-1..N-9 with the bottom envelope entries
   {
-    double tl[9][5], te[10];
+    double tl[9][4], te[10];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-#pragma unroll
-      for (int t = 0; t < 5; ++t) tl[i][t] = V(n - 9 + i, t);  // L(row, row - 4 + t)
+    for (int i = 0; i < 9; ++i) quad(n - 9 + i, 0, tl[i]);  // L(row, row - 4 + t)
 #pragma unroll
     for (int e = 0; e < 10; ++e) te[e] = edge[(size_t)(10 + e) * nops];
 #pragma unroll
@@ -1552,13 +1593,12 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
     }
   }
   {
-    // bulk rows N-10..0: L(j + t, j) = slot 4 - t of row j + t
+    // bulk rows N-10..0: the L column below row j (L(j + t, j) at t)
     double fl[kPfT][5];
 #pragma unroll
     for (int r = 0; r < kPfT; ++r) {
       const int j = n - 10 - r >= 0 ? n - 10 - r : 0;
-#pragma unroll
-      for (int t = 1; t <= 4; ++t) fl[r][t] = V(j + t, 4 - t);
+      quad(j, 2, fl[r] + 1);
     }
     Cd x1 = C(n - 9), x2 = C(n - 8), x3 = C(n - 7), x4 = C(n - 6);
 #pragma unroll kUnrollRows
@@ -1579,8 +1619,7 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
           C(j) = x;
         }
         const int jn = j - kPfT >= 0 ? j - kPfT : 0;
-#pragma unroll
-        for (int t = 1; t <= 4; ++t) fl[r][t] = V(jn + t, 4 - t);
+        quad(jn, 2, fl[r] + 1);
       }
     }
   }
@@ -1597,9 +1636,12 @@ k_adj_sweep(Dims d, Grid g, Factors fv, Factors ft, Factors fp, int kind,
   extern __shared__ __align__(16) unsigned char smem[];
   Cd *col = reinterpret_cast<Cd *>(smem);
   const int lane = threadIdx.x;
+  const int comp = blockIdx.y;
+  // the factor family depends only on the launch and the system, so that its
+  // base addresses stay uniform (scalar buffer resources)
+  const Factors F = kind == 1 ? fp : (comp == 3 ? ft : fv);
   const int md = blockIdx.x * kSweepLanes + lane;
   if (md >= d.nmodes) return;
-  const int comp = blockIdx.y;
   const size_t P = d.nmodes;
   const int n = NR > 0 ? NR : d.nr;
   const int kp1 = d.kmax + 1;
@@ -1611,18 +1653,15 @@ k_adj_sweep(Dims d, Grid g, Factors fv, Factors ft, Factors fp, int kind,
   auto C = [&](int j) -> Cd & { return col[j * kSweepLanes + lane]; };
   const double2 *xb = src + (size_t)(kind == 0 ? comp : 0) * n * P + md;
   double2 *out = dst + (size_t)(kind == 0 ? comp : 0) * n * P + md;
-  Factors F = fv;
   int op = 0;
   if (kind == 1) {
     if (zero) {
       for (int j = 0; j < n; ++j) st(out + (size_t)j * P, Cd{0, 0});
       return;
     }
-    F = fp;
     op = m * kp1 + ka;
     for (int j = 0; j < n; ++j) C(j) = ld(xb + (size_t)j * P);
   } else if (comp == 3) {
-    F = ft;
     op = m * kp1 + ka;
     for (int j = 0; j < n; ++j) C(j) = ld(xb + (size_t)j * P);
   } else if (zero) {
@@ -1959,9 +1998,11 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
   const bool lds = col_bytes <= 64 * 1024;
   const dim3 lg((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, c->d.heated ? 4 : 3);
   const dim3 lg1((c->d.nmodes + kSweepLanes - 1) / kSweepLanes, 1);
-  const bool unrolled = lds && c->d.nr == 64;
+  // the unrolled sweeps read the packed factors (present where they run)
+  const bool unrolled = lds && c->fv.pc;
+  auto adj_sweep = c->d.nr == 64 ? k_adj_sweep<64> : k_adj_sweep<32>;
   if (unrolled)
-    hipLaunchKernelGGL(k_adj_sweep<64>, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+    hipLaunchKernelGGL(adj_sweep, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
                        c->fv, c->ft, c->fp, 0, sx, lam, sf);
   else if (lds)
     hipLaunchKernelGGL(k_adj_sweep<0>, lg, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
@@ -1971,7 +2012,7 @@ hipError_t launch_solve_vjp(const nsc_ctx *c, const double *ubar_out, double *ub
                        c->g, c->fv, c->ft, sx, lam, sf);
   hipLaunchKernelGGL(k_adj_pbar, mode_grid(c, c->d.nr), dim3(256), 0, c->stream, c->d, c->g, sf, sp);
   if (unrolled)
-    hipLaunchKernelGGL(k_adj_sweep<64>, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
+    hipLaunchKernelGGL(adj_sweep, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,
                        c->fv, c->ft, c->fp, 1, sp, lam, sg);
   else if (lds)
     hipLaunchKernelGGL(k_adj_sweep<0>, lg1, dim3(kSweepLanes), col_bytes, c->stream, c->d, c->g,

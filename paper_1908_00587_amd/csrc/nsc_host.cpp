@@ -172,11 +172,22 @@ int alloc_factors(Factors *f, int nq, int kp1, int nr, bool packed) {
   return NSC_OK;
 }
 
+// The packed columns of a family with packed rows (the adjoint's transposed
+// sweeps), zero where a column entry falls outside the matrix.
+int alloc_columns(Factors *f, int nr) {
+  if (!f->pk) return NSC_OK;
+  const size_t bytes = (size_t)nr * 8 * f->nops * sizeof(double);
+  TRY(dmalloc((void **)&f->pc, bytes));
+  HIPCHK(hipMemset(f->pc, 0, bytes));
+  return NSC_OK;
+}
+
 void free_factors(Factors *f) {
   if (f->vals) (void)hipFree(f->vals);
   if (f->edge) (void)hipFree(f->edge);
   if (f->pk) (void)hipFree(f->pk);
-  f->vals = f->edge = f->pk = nullptr;
+  if (f->pc) (void)hipFree(f->pc);
+  f->vals = f->edge = f->pk = f->pc = nullptr;
 }
 
 int ensure_factors(nsc_ctx *c, double dt, double cc) {
@@ -590,6 +601,9 @@ static int init_impl(nsc_ctx *c, double eta, double Re_i, double Re_o, double Ra
   c->inf.nops = d.mt * kp1;
   TRY(dmalloc((void **)&c->inf.resp, (size_t)8 * n * c->inf.nops * sizeof(double)));
   TRY(dmalloc((void **)&c->inf.ainv, (size_t)4 * c->inf.nops * sizeof(double)));
+  TRY(alloc_columns(&c->fv, n));
+  TRY(alloc_columns(&c->fp, n));
+  if (d.heated) TRY(alloc_columns(&c->ft, n));
 
   // Delta t-independent pressure factors (slot (0,0): the mean pressure head)
   HIPCHK(launch_factor(c, &c->fp, OP_POISSON, 0.0, 0.0));

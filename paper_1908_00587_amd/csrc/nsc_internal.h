@@ -61,13 +61,17 @@ __host__ __device__ __forceinline__ int odd_off(const Grid &g, int q) { return (
 
 // Compact no-pivot LU factors of a family of radial operators.
 // vals: [N_r][kSlots][nops], edge: [kEdge][nops]; op = q * (K+1) + |k|.
-// pk (only where the fully unrolled sweeps run, else null): the same rows
-// packed per operator, [N_r][2][nops][4] = L slots 0-3, then U slots 5-8,
-// so that a lane fetches four entries of a row with two 16-byte loads.
+// pk and pc (only where the fully unrolled sweeps run, else null): the band
+// entries packed per operator, so that a lane fetches four of them with two
+// 16-byte loads.  pk: [N_r][2][nops][4], the L row (slots 0-3) and the U row
+// (slots 5-8) of row j; pc: [N_r][2][nops][4], the L column below the
+// diagonal (L(j+t, j), t = 1..4) and the U column above it (U(j-t, j)),
+// zero outside the matrix (the transposed sweeps of the adjoint).
 struct Factors {
   double *vals = nullptr;
   double *edge = nullptr;
   double *pk = nullptr;
+  double *pc = nullptr;
   int nq = 0;   // number of q values
   int nops = 0;
 };
