@@ -11,8 +11,8 @@ Fourier--Galerkin in theta and z with 3/2-rule dealiased pseudospectral
 products, high-order (9-point) finite differences in r, a predictor--corrector
 time integrator with variable time step, Boussinesq heat transfer, and
 divergence-free initial conditions (Functionality, section 2.1).  The paper
-prints no equations; every formula here is a reading written down in
-DESIGN.md ("Readings of the paper").  Floating point is IEEE FP64 throughout.
+prints no equations; every formula here is a reading of its description,
+stated where the formula is written.  Floating point is IEEE FP64 throughout.
 Transforms are explicit DFT matrices (dense matmul), the radial systems are
 dense LU solves (``torch.linalg.solve``), the time step is the explicit
 predictor--corrector loop.  Written in plain PyTorch CPU ops so that autograd

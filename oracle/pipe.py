@@ -8,7 +8,7 @@ The paper ships a version of the method for flows in straight pipes that
 keeps its numerical method and infrastructure (abstract; section 4,
 "Impact"), with the pipe formulation of another code whose description is
 not part of the paper.  Every pipe-specific formula below is therefore a
-reading (listed in DESIGN.md):
+reading:
 
   * geometry and units: a pipe of radius 1, periodic in z with period L_z;
     time in R^2/nu, velocity in nu/R; the flow is driven by a constant mean

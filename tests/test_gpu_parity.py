@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle
 on the same seeded inputs.  FP64 bar: relative max-norm deviation <= 1e-12
-(a few ulp of FP64 amplified by the conditioning of the radial operators;
-derivation in DESIGN.md, "Tolerances")."""
+(a few ulp of FP64 amplified by the conditioning of the radial operators,
+whose condition numbers grow with N_r)."""
 import math
 import sys
 
