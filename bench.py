@@ -384,6 +384,43 @@ def run_cpu(wname, steps):
                 cpu_model=model, affinity_cpus=ncpu)
 
 
+def run_cpu_fast(wname, steps):
+    """The same step on the host, evaluated the way a CPU code would
+    (oracle.fast: FFTs over every host thread, radial systems inverted once
+    per step size and batched over the modes), with the workload's time-step
+    control; the inversions for the first step size are done before the
+    clock starts, later ones (on a change of step size) are timed."""
+    import torch
+
+    import oracle as O
+    from oracle.fast import Stepper
+    from paper_1908_00587_amd.workloads import WORKLOADS, amplitudes, params
+
+    w = WORKLOADS[wname]
+    p = O.Params(*params(wname))
+    u = O.initial_state(p, amplitudes(wname))
+    s = Stepper(p)
+    dt = w["dt"]
+    if w["dynamic"]:
+        dt = min(w["dt"], 0.5 * s.nonlinear(u)[1])
+    s.set_dt(dt)
+    changes = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, dtc = s.step(u, dt)
+        if w["dynamic"]:
+            nd = O.next_dt(dt, dtc, 0.5, w["dt"])
+            changes += nd != dt
+            dt = nd
+    el = time.perf_counter() - t0
+    model, ncpu = host_cpu()
+    return dict(value=steps / el, unit="steps/s", cores=s.workers, kind="oracle-fast",
+                torch_threads=torch.get_num_threads(),
+                sample=f"{steps} FP64 steps of {wname} (FFTs, per-step-size inverses, "
+                       f"{changes} step-size changes), {el:.1f} s",
+                cpu_model=model, affinity_cpus=ncpu)
+
+
 RESTART_FROM = "tc-heated-n64"
 RESTART_TO = (96, 96, 191)  # N_r, M_theta, M_z after the restart
 
@@ -575,6 +612,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tc-heated-n64")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-fast-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-config", action="store_true",
                     help="time the main workload only")
@@ -616,6 +654,7 @@ def main():
     adj = (run_adjoint(args.adjoint_steps, ckpt=args.adjoint_ckpt)
            if args.adjoint_steps > 0 else None)
     cpu = None if args.no_cpu else run_cpu(args.workload, args.cpu_steps)
+    cpu_fast = None if args.no_cpu else run_cpu_fast(args.workload, args.cpu_fast_steps)
     mx = g["mixed"]
     fp = g.get("fp64", {})
     out = {
@@ -648,6 +687,7 @@ def main():
         "per_config": per,
         "adjoint_forward_cost_ratio": adj,
         "cpu_baseline": cpu,
+        "cpu_fast": cpu_fast,
     }
     print(json.dumps(out), flush=True)
 

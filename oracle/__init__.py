@@ -17,6 +17,10 @@ Transforms are explicit DFT matrices (dense matmul), the radial systems are
 dense LU solves (``torch.linalg.solve``), the time step is the explicit
 predictor--corrector loop.  Written in plain PyTorch CPU ops so that autograd
 provides an independent gradient for the adjoint tests.
+
+``oracle.fast`` evaluates the same step faster on the host (FFTs, radial
+systems inverted once per step size) for the benchmark's CPU reference
+figure; the CPU tests hold it to ``oracle.tc``.
 """
 from .tc import (  # noqa: F401
     Params, radial_grid, fornberg, fd_matrices, cc_weights, to_physical,
