@@ -611,8 +611,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="tc-heated-n64")
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--cpu-fast-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-fast-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-config", action="store_true",
                     help="time the main workload only")
