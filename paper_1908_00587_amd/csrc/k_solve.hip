@@ -554,6 +554,15 @@ __global__ void __launch_bounds__(256) k_rhs(Dims d, Grid g, const double2 *__re
 // loads past it return zero.
 constexpr int kBufferWord3 = 0x00020000;
 
+// Raw buffer resource over `bytes` bytes of factor data at base, for the
+// fully unrolled sweeps (NR > 0), whose factor arrays the host keeps below
+// 2^31 bytes; the other variants never read through it and get an empty one.
+template <int NR>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sweep_rsrc(const double *base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), 0,
+                                           NR > 0 ? (int)bytes : 0, kBufferWord3);
+}
+
 struct SweepSys {
   Factors F;
   int qmode;   // 0: q = m, 1: q = m + 1, 2: q = |m - 1|
@@ -642,9 +651,8 @@ k_sweep(Dims d, SweepArgs a) {
   // in a scalar register, so no 64-bit address is formed per load and the
   // registers go to rows in flight (the host picks this variant only while
   // the factor array spans less than 2^31 bytes).
-  const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<double *>(F.vals), 0, (int)((size_t)n * kSlots * nops * sizeof(double)),
-      kBufferWord3);
+  const __amdgpu_buffer_rsrc_t frs =
+      sweep_rsrc<NR>(F.vals, (size_t)n * kSlots * nops * sizeof(double));
   const int voff = op * (int)sizeof(double);
   auto row = [&](int j, int sl) -> double {
     if constexpr (NR > 0)
@@ -658,8 +666,7 @@ k_sweep(Dims d, SweepArgs a) {
   // of row j into o[0..3].  Unrolled: two 16-byte loads from the row-packed
   // copy, so that a row costs three memory instructions with its right side
   // or its diagonal instead of five.
-  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
-      F.pk, 0, (int)((size_t)n * 8 * nops * sizeof(double)), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t prs = sweep_rsrc<NR>(F.pk, (size_t)n * 8 * nops * sizeof(double));
   const int poff = op * (int)(4 * sizeof(double));
   auto quad = [&](int j, int part, double *o) {
     if constexpr (NR > 0) {
@@ -1482,10 +1489,9 @@ __device__ __forceinline__ void sweep_t_lds(const Factors &F, int op, int nrt, C
   // row) and columns (2: L below the diagonal, 3: U above it), two 16-byte
   // loads per part; else the compact rows.
   const size_t n8 = (size_t)n * nops * sizeof(double);
-  const __amdgpu_buffer_rsrc_t rv =
-      __builtin_amdgcn_make_buffer_rsrc(F.vals, 0, (int)(n8 * kSlots), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(F.pk, 0, (int)(n8 * 8), kBufferWord3);
-  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(F.pc, 0, (int)(n8 * 8), kBufferWord3);
+  const __amdgpu_buffer_rsrc_t rv = sweep_rsrc<NR>(F.vals, n8 * kSlots);
+  const __amdgpu_buffer_rsrc_t rk = sweep_rsrc<NR>(F.pk, n8 * 8);
+  const __amdgpu_buffer_rsrc_t rc = sweep_rsrc<NR>(F.pc, n8 * 8);
   const int o8 = op * (int)sizeof(double);
   auto dg = [&](int j) -> double {  // 1/U_jj
     if constexpr (NR > 0)
